@@ -1,0 +1,141 @@
+"""Benchmark of the U(1)xU(1) lattice update on one MI355X.
+
+Workload (one step = one leapfrog step of the whole box, both sectors, with
+the fused diagnostics every 10th step): 512^3 periodic box, dx = 0.5,
+dt = 0.1, radiation era (m = 1/2), s = 1, lambda = 2, e = 1, sigma = 1,
+kappa = 0.9, seeded random-phase initial conditions, FP32 fields with FP64
+reductions, a = 1 at eta = 128.  Warm-up steps run from eta = 1; the timed
+steps continue the same run (the default 10 + 1260 steps reach eta = 128).
+
+Printed: one JSON line with site-updates/s, the HBM roofline of the update
+kernel (timed with HIP events around each launch on the library's stream),
+an FP64 leg of the same box, and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "site-updates/s & % HBM roofline, FP32 vs FP64, 512^3 box and batched ensemble"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_SITE = {"fp32": 160, "fp64": 320}   # 20 reals read + 20 written per site-update
+
+
+def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0.5, s=1.0, eta_ref=128.0, seed=1):
+    params = P.make_params(n, precision=precision, eta_ref=eta_ref, diag_every=diag_every)
+    lat = P.Lattice(params, device="cuda:0")
+    lat.init_fields(seed)
+    lat.step(warmup, eta0, era_m, s)
+    lat.diagnostics()
+    torch.cuda.synchronize()
+    lat.timing_read()
+    lat.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps, eta0 + warmup * params.dt, era_m, s)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tm = lat.timing_read()
+    recs = lat.diagnostics()
+    lat.timing_enable(False)
+    sites = n ** 3
+    wall = t1 - t0
+    kern_ms = tm["ms_plain"] / max(tm["n_plain"], 1)
+    achieved = BYTES_PER_SITE[precision] * sites / (kern_ms * 1e-3) / 1e9
+    out = {
+        "value": sites * steps / wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "kernel_ms": kern_ms,
+        "diag_step_kernel_ms": tm["ms_diag"] / max(tm["n_diag"], 1),
+        "diag_post_ms": tm["ms_post"] / max(tm["n_diag"], 1),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "last_record": {k: recs[-1][k] for k in ("eta", "xi_W", "xi_lag", "v2_lag", "f_total", "gauss_rel")}
+        if recs else None,
+    }
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline():
+    """The FP64 oracle on a bounded sample of the workload: a 128^3 box with the same
+    schedule (radiation era, s = 1, a = 1 at eta = 128), 20 steps with the diagnostics
+    every 10th step, on all host threads OpenMP gives it."""
+    import oracle as O
+
+    n, steps = 128, 20
+    m = O.model(n, eta_ref=128.0)
+    st = O.init_random_phase(m, 1)
+    t0 = time.perf_counter()
+    O.run(m, st, steps, 1.0, 0.5, 1.0, diag_every=10)
+    dt = time.perf_counter() - t0
+    return {"value": n ** 3 * steps / dt, "unit": "site-updates/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{n}^3 box, {steps} steps from eta=1 (m=1/2, s=1, diagnostics every 10), FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1260)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--fp64-steps", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this implementation runs on one GPU only (the lattice is not sharded); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2208_01525_amd as P
+
+    fp32 = run_box(P, torch, args.n, "fp32", args.warmup, args.steps, diag_every=10)
+    print(f"fp32: {fp32['value']:.4g} site-updates/s, kernel {fp32['kernel_ms']:.3f} ms, "
+          f"{fp32['roofline']['frac']:.3f} of HBM peak", file=sys.stderr, flush=True)
+    fp64 = run_box(P, torch, args.n, "fp64", args.warmup, args.fp64_steps, diag_every=10) if args.fp64_steps else None
+    if fp64:
+        print(f"fp64: {fp64['value']:.4g} site-updates/s, kernel {fp64['kernel_ms']:.3f} ms, "
+              f"{fp64['roofline']['frac']:.3f} of HBM peak", file=sys.stderr, flush=True)
+    cpu = None if args.no_cpu else cpu_baseline()
+
+    line = {
+        "metric": METRIC,
+        "value": fp32["value"],
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": fp32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.n}^3 periodic box, radiation era (m=1/2), s=1, eta 1->128, dx=0.5, dt=0.1, "
+                               "lambda=2, e=1, sigma=1, kappa=0.9, random-phase ICs (seed 1), FP32 fields + FP64 "
+                               "reductions, diagnostics every 10 steps",
+                   "sites": args.n ** 3},
+        "roofline": fp32["roofline"],
+        "cpu_baseline": cpu,
+        "kernel_ms": fp32["kernel_ms"],
+        "diag_step_kernel_ms": fp32["diag_step_kernel_ms"],
+        "diag_post_ms": fp32["diag_post_ms"],
+        "fp64": {"value": fp64["value"], "unit": "site-updates/s", "steps": args.fp64_steps,
+                 "ms_per_step": fp64["ms_per_step"], "kernel_ms": fp64["kernel_ms"],
+                 "roofline": fp64["roofline"]} if fp64 else None,
+        "last_record": fp32["last_record"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

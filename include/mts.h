@@ -1,0 +1,193 @@
+/*
+ * mts.h -- C ABI of libmts: the per-timestep lattice update of the
+ * U(1)xU(1) multitension cosmic-string model of Correia & Martins,
+ * arXiv:2208.01525, with its fused network diagnostics, on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Conventions
+ *   - Every function returns int: MTS_OK (0) or a negative MTS_E* code.
+ *     No C++ exception crosses this boundary.  The text of the last error
+ *     of a context is available from mts_last_error().
+ *   - Pointers marked "device" are HIP device addresses; "host" pointers
+ *     are ordinary CPU memory.  Sizes are in bytes unless stated.
+ *   - All GPU work of a context is enqueued on the HIP stream given at
+ *     creation (NULL = the null stream).  Functions that return host data
+ *     (mts_diagnostics, mts_get_*) synchronise that stream first.
+ *   - A context is not thread-safe: one host thread at a time.
+ *
+ * Lattice and notation (Sec. II-III of the paper)
+ *   Periodic comoving box nx*ny*nz, spacing dx (= h), conformal time step
+ *   dt (= k).  Sector p: complex scalar phi, momentum Pi, gauge links A_i,
+ *   electric field E_i.  Sector q: psi, Psi, B_i, H_i.  `s` is the
+ *   paper's beta: coupling constants scale as a^{-2(1-s)} (Sec. III);
+ *   s = 1 is physical evolution, s = 0 is constant comoving width (PRS),
+ *   s < 0 is core growth.  era_m is the exponent of a ~ t^m, so
+ *   a = (eta / eta_ref)^p with p = m / (1 - m), normalised to a = 1 at
+ *   eta_ref (the end of the run: Sec. V fixes a = 1 at the end).
+ *
+ * Host field exchange format (mts_get_fields / mts_set_fields)
+ *   double[20][nz][ny][nx], x fastest.  Planes:
+ *      0-1 phi (re, im)    2-3 psi     4-5 Pi      6-7 Psi
+ *      8-10 A_x,A_y,A_z    11-13 B     14-16 E     17-19 H
+ *   The momenta are the half-step values Pi^{n-1/2}, E^{n-1/2} that the
+ *   leapfrog stores between steps.
+ */
+#ifndef MTS_H
+#define MTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ codes */
+#define MTS_OK 0
+#define MTS_EINVAL (-1)      /* bad argument or parameter                       */
+#define MTS_EUNSTABLE (-2)   /* time step violates the leapfrog stability bound */
+#define MTS_ENOMEM (-3)      /* device allocation failed / buffer too small     */
+#define MTS_EHIP (-4)        /* a HIP runtime call failed (see mts_last_error)  */
+#define MTS_ENONFINITE (-5)  /* a diagnostic reduction saw NaN or Inf           */
+
+#define MTS_FP32 1           /* fields and per-site arithmetic in float;
+                                reductions and time bookkeeping in double      */
+#define MTS_FP64 2           /* everything in double                            */
+
+/* ----------------------------------------------------------- params */
+typedef struct mts_params {
+    int32_t nx, ny, nz;      /* box, each >= 4; nx*ny*nz < 2^32                 */
+    int32_t precision;       /* MTS_FP32 or MTS_FP64                            */
+    double dx;               /* lattice spacing h > 0        (paper: 0.5)       */
+    double dt;               /* conformal time step k > 0    (paper: 0.1)       */
+    double lambda_p, lambda_q;  /* scalar couplings lambda_0 >= 0   (2, 2)      */
+    double e_p, e_q;         /* gauge couplings e_0 > 0         (1, 1)          */
+    double sigma_p, sigma_q; /* vacuum expectation values > 0   (1, 1)          */
+    double kappa;            /* potential coupling kappa_0      (0.9)           */
+    double eta_ref;          /* a(eta_ref) = 1; > 0                             */
+    int32_t diag_every;      /* diagnostics every d steps; 0 = never            */
+    int32_t overlap_radius;  /* fast-method overlap tolerance in cells: 0 or 1  */
+} mts_params;
+
+/* One diagnostic record of integer time eta_n: fields phi^n, A^n; momenta
+ * time-centred (Pi^{n-1/2} + Pi^{n+1/2})/2; Gauss residual at n+1/2.
+ * Sums are FP64 reductions over all sites (Sec. III.A-B, Sec. IV). */
+typedef struct mts_diag {
+    int64_t step;            /* global step index n since mts_init_fields       */
+    double eta;              /* eta_n                                           */
+    double a;                /* scale factor a(eta_n)                           */
+    double s;                /* beta of this step                               */
+    double sum_energy;       /* h^3 sum eps,  eps = K + G + a^{-2s}(Kg+Bg) + a^{2s} V */
+    double sum_lagrangian;   /* h^3 sum Lag,  Lag = K - G + a^{-2s}(Kg-Bg) - a^{2s} V */
+    double sum_KL, sum_GL;   /* sum K*Lag, sum G*Lag    (velocity, all strings) */
+    double sum_KV, sum_GV;   /* sum K*Vint, sum G*Vint  (velocity, pq strings)  */
+    double gauss_abs[2];     /* sum |C_sigma|, C = div E - g Im[phi* Pi]        */
+    double gauss_scale[2];   /* sum (|div E| + |g Im[phi* Pi]|)                 */
+    int64_t wind_abs[2];     /* sum over plaquettes of |winding|, p and q       */
+    int64_t pq_count2;       /* count_p + count_q = 2 N_pq (overlapping cells)  */
+    /* derived on the host from the sums above (Sec. III.A):                    */
+    double L_p, L_q, L_pq;   /* L_pq = h N_pq; L_p = h sum|W_p| - L_pq          */
+    double xi_p, xi_q, xi_pq, xi_W;   /* sqrt(V/L)                              */
+    double xi_lag;           /* sqrt(-2 pi V / (h^3 sum Lag)), mu = 2 pi sigma^2 */
+    double f_total, f_p;     /* L_pq/(L_pq+L_p+L_q), L_pq/L_p                   */
+    double v2_lag, v2_pq;    /* <v^2> = 2R/(1+R), R = sum K W / sum G W         */
+    double gauss_rel[2];     /* gauss_abs / gauss_scale (0 when scale is 0)     */
+    int32_t flags;           /* bit 0: non-finite sum; bit 1: records were lost */
+    int32_t pad;
+} mts_diag;
+
+typedef struct mts_ctx mts_ctx;
+
+/* Bytes of the device state buffer a context needs: 30 planes of
+ * nx*ny*nz (rounded up to 64) elements of the precision's type -- the 20
+ * live components plus a second copy of the 10 field components (the
+ * drift writes the new fields into the other copy). */
+size_t mts_state_bytes(const mts_params *p);
+
+/* Create a context on the current HIP device.
+ *   p           parameters, copied.  EINVAL for dims < 4, non-positive
+ *               dx/dt/e/sigma/eta_ref, negative lambda, precision or
+ *               overlap_radius out of range, diag_every < 0.
+ *   dev_state   device buffer of at least mts_state_bytes(p) bytes,
+ *               256-byte aligned, owned by the caller and borrowed for the
+ *               context's lifetime (its contents are the lattice).
+ *   stream      hipStream_t (as void*), NULL for the null stream.
+ *   out         receives the context.
+ * The library allocates its own device scratch (reduction partials,
+ * winding and cell bytes: 4 bytes per site, diagnostic ring); ENOMEM if
+ * that fails. */
+int mts_create(const mts_params *p, void *dev_state, size_t state_bytes, void *stream, mts_ctx **out);
+
+/* Release the library's scratch.  The caller's state buffer is untouched. */
+int mts_destroy(mts_ctx *ctx);
+
+/* Random-phase initial conditions (Sec. III): |phi| = sigma_p, |psi| =
+ * sigma_q, phases iid uniform in [0, 2 pi) from SplitMix64 (draw number
+ * sector*S + site of the stream seeded with `seed`, top 53 bits times
+ * 2 pi, cos/sin in double), all momenta, links and electric fields zero.
+ * Resets the step counter and drops undrained diagnostic records. */
+int mts_init_fields(mts_ctx *ctx, uint64_t seed);
+
+/* Advance n >= 0 leapfrog steps from conformal time eta (step j runs from
+ * eta + j*dt), in era m (0 <= m < 1) with beta = s (Sec. III):
+ *   (1+delta) Pi^{n+1/2} = (1-delta) Pi^{n-1/2}
+ *                          + dt [D^-D^+ phi - a^{2s} phi (lambda/2 (|phi|^2 - sigma^2)
+ *                                                        - kappa (|psi|^2 - sigma_q^2))]
+ *   (1+omega) E^{n+1/2}  = (1-omega) E^{n-1/2} + dt [-d^-F + 2 e^2 a^{2s} Im(phi* D^+ phi)]
+ *   phi^{n+1} = phi^n + dt Pi^{n+1/2},   A^{n+1} = A^n + dt E^{n+1/2}
+ * with delta = p dt / eta (alpha = 2), omega = (1 - s) delta, and the same
+ * for psi, B (compact links U = exp(-i h A), plaquette sines for F).
+ * A step whose global index is a multiple of diag_every also records
+ * the diagnostics of its starting time.
+ *   EINVAL     n < 0, m outside [0, 1), eta <= 0 with m > 0.
+ *   EUNSTABLE  dt^2 (12/h^2 + a_max^{2s} mu2_max) >= 4 for the a-range of
+ *              the call, mu2_max = max(2 e^2 sigma^2, eigenvalues of the
+ *              vacuum scalar mass matrix); nothing is launched. */
+int mts_step(mts_ctx *ctx, int32_t n, double eta, double era_m, double s);
+
+/* Drain the diagnostic records produced since the last call (oldest
+ * first), synchronising the stream.  Writes at most `max` records to the
+ * host array `out` and their number to *count.  Records that did not fit
+ * the device ring (4096 entries) are lost and flagged.  Returns
+ * ENONFINITE (after writing the records) if any record has a non-finite
+ * sum. */
+int mts_diagnostics(mts_ctx *ctx, mts_diag *out, int32_t max, int32_t *count);
+
+/* Copy the lattice to / from the host exchange format (double[20][S],
+ * host memory of 20*S doubles).  Values are converted to / from the
+ * context's precision.  Synchronous. */
+int mts_get_fields(mts_ctx *ctx, double *host);
+int mts_set_fields(mts_ctx *ctx, const double *host);
+
+/* Signed plaquette windings of the current fields (Sec. III.A), host
+ * int8[6][S]: sector p (W_x, W_y, W_z), then sector q; W_rho is the
+ * winding through the face normal to rho at the cell's lower corner,
+ * clamped to [-127, 127].  Synchronous; allocates 6 bytes per site of
+ * temporary device memory. */
+int mts_get_windings(mts_ctx *ctx, int8_t *host);
+
+/* Cell values of the last diagnostic step (total |winding| through the
+ * six faces of each cell; a straight string gives 2, Sec. III.B), host
+ * uint8[2][S] (sector p, then q).  Synchronous. */
+int mts_get_cells(mts_ctx *ctx, uint8_t *host);
+
+/* Kernel timing with HIP events on the context's stream.  While enabled,
+ * every launch of the update kernel is bracketed by events; the summary
+ * returns the launch count and the summed event time in milliseconds of
+ * plain steps and of diagnostic steps, and the summed time of the
+ * diagnostic post-kernels (windings/Gauss, cells, overlap, final reduce).
+ * mts_timing_read synchronises the stream and resets the counters. */
+int mts_timing_enable(mts_ctx *ctx, int32_t on);
+int mts_timing_read(mts_ctx *ctx, int64_t *n_plain, double *ms_plain, int64_t *n_diag, double *ms_diag,
+                    double *ms_post);
+
+/* Text of the last error of ctx (never NULL). */
+const char *mts_last_error(const mts_ctx *ctx);
+
+/* Short name of a return code. */
+const char *mts_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MTS_H */

@@ -1,0 +1,104 @@
+// kernels.h -- internal interface between the host library (api.hip) and the
+// gfx950 kernels (kernels.hip) of the U(1)xU(1) lattice update.
+//
+// Device state layout (one buffer owned by the caller), in units of
+// `plane` elements of T (plane = sites rounded up to 64):
+//   [ 0,10)  field copy 0: phi (cx, 2 planes), psi (cx, 2), A_x,A_y,A_z, B_x,B_y,B_z
+//   [10,20)  field copy 1: same order (the drift writes the other copy)
+//   [20,30)  momenta:      Pi (cx, 2), Psi (cx, 2), E_x,E_y,E_z, H_x,H_y,H_z
+// Complex fields are interleaved (re, im); everything is structure of
+// arrays with x fastest, site = x + nx (y + ny z).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mts {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+    T re, im;
+};
+
+template <typename T>
+struct Fields {           // one copy of the fields, by sector (0 = p, 1 = q)
+    cx<T> *phi[2];
+    T *A[2][3];
+};
+
+template <typename T>
+struct Moms {             // momenta at half steps, by sector
+    cx<T> *pi[2];
+    T *E[2][3];
+};
+
+struct Geom {
+    int32_t nx, ny, nz;
+    uint32_t nxy;         // nx * ny
+};
+
+// Per-step coefficients, computed in double on the host and cast to T once.
+template <typename T>
+struct StepCoef {
+    T h, inv_h, inv_h2, inv_h3, k;
+    T cpi, kpi;           // (1 - delta)/(1 + delta), k/(1 + delta)
+    T cE, kE;             // (1 - omega)/(1 + omega), k/(1 + omega)
+    T lamh[2];            // a^{2s} lambda_0 / 2
+    T kap;                // a^{2s} kappa_0
+    T sig2[2];            // sigma^2
+    T cur[2];             // 2 e_0^2 a^{2s} / h
+    // integer-time diagnostics
+    T a2s, am2s;          // a^{2s}, a^{-2s}
+    T inv_2e2[2];         // 1 / (2 e_0^2)
+    T inv_e2h4[2];        // 1 / (e_0^2 h^4)
+    T lam4[2];            // lambda_0 / 4
+    T kap0;               // kappa_0
+};
+
+// Reduction slots of one diagnostic record (FP64 partials per block).
+enum Slot {
+    SL_EPS = 0, SL_LAG, SL_KL, SL_GL, SL_KV, SL_GV,
+    SL_GAUSS_ABS_P, SL_GAUSS_ABS_Q, SL_GAUSS_SCALE_P, SL_GAUSS_SCALE_Q,
+    SL_WIND_P, SL_WIND_Q, SL_OV_P, SL_OV_Q,
+    NSLOT = 16
+};
+
+// Where the partials of one diagnostic step go.
+struct Partials {
+    double *base;         // [NSLOT][maxblk]
+    uint32_t maxblk;
+};
+
+// ---- launch wrappers (all enqueue on `st`, return the launch error) ----
+
+// One leapfrog step: reads `in` (fields at n) and `mom` (momenta at n-1/2),
+// writes momenta n+1/2 in place and fields n+1 into `out`.  With diag,
+// also the integer-time energy / Lagrangian / velocity sums.
+template <typename T>
+hipError_t launch_step(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, const StepCoef<T> &c,
+                       bool diag, Partials part, hipStream_t st);
+
+// Windings of `f` (packed |W| per sector into wabs[2][plane] bytes, sum |W|
+// into partials) and the Gauss residual of (f, mom) with g_sigma.
+// If `signed_out` is non-null the signed windings go there as int8[6][plane]
+// and nothing else is written.
+template <typename T>
+hipError_t launch_wind_gauss(const Geom &g, Fields<T> f, Moms<T> mom, T h, const double gcoef[2],
+                             uint8_t *wabs, uint32_t plane, int8_t *signed_out, Partials part, hipStream_t st);
+
+// Cell values from packed |W| (cells[2][plane] bytes), then the overlap counts.
+hipError_t launch_cells(const Geom &g, const uint8_t *wabs, uint8_t *cells, uint32_t plane, hipStream_t st);
+hipError_t launch_overlap(const Geom &g, const uint8_t *cells, uint32_t plane, int radius, Partials part,
+                          hipStream_t st);
+
+// Fixed-order FP64 sum of every slot's partials into rec[NSLOT].
+hipError_t launch_reduce(Partials part, const uint32_t *nblk_per_slot_dev, double *rec, hipStream_t st);
+
+// Random-phase initial conditions into field copy `f` and momenta `mom`.
+template <typename T>
+hipError_t launch_init(const Geom &g, Fields<T> f, Moms<T> mom, uint64_t seed, double sig_p, double sig_q,
+                       hipStream_t st);
+
+// Number of blocks the per-site kernels use for geometry g (partials needed).
+uint32_t site_blocks(const Geom &g);
+
+}  // namespace mts

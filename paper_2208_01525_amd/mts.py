@@ -1,0 +1,214 @@
+"""Thin Python binding of libmts (include/mts.h): argument marshalling only.
+
+Every step of the lattice update and of the diagnostics runs in the HIP
+kernels of libmts.so; PyTorch only allocates the device state buffer and
+supplies the stream.  The library must have been built
+(``python -m paper_2208_01525_amd.build`` or ``__graft_entry__.build()``);
+loading fails loudly otherwise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmts.so")
+
+MTS_OK, MTS_EINVAL, MTS_EUNSTABLE, MTS_ENOMEM, MTS_EHIP, MTS_ENONFINITE = 0, -1, -2, -3, -4, -5
+MTS_FP32, MTS_FP64 = 1, 2
+
+EXPORTS = ("mts_state_bytes", "mts_create", "mts_destroy", "mts_init_fields", "mts_step", "mts_diagnostics",
+           "mts_get_fields", "mts_set_fields", "mts_get_windings", "mts_get_cells", "mts_timing_enable",
+           "mts_timing_read", "mts_last_error", "mts_strerror")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dt", ctypes.c_double),
+        ("lambda_p", ctypes.c_double), ("lambda_q", ctypes.c_double),
+        ("e_p", ctypes.c_double), ("e_q", ctypes.c_double),
+        ("sigma_p", ctypes.c_double), ("sigma_q", ctypes.c_double),
+        ("kappa", ctypes.c_double), ("eta_ref", ctypes.c_double),
+        ("diag_every", ctypes.c_int32), ("overlap_radius", ctypes.c_int32),
+    ]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64), ("eta", ctypes.c_double), ("a", ctypes.c_double), ("s", ctypes.c_double),
+        ("sum_energy", ctypes.c_double), ("sum_lagrangian", ctypes.c_double),
+        ("sum_KL", ctypes.c_double), ("sum_GL", ctypes.c_double),
+        ("sum_KV", ctypes.c_double), ("sum_GV", ctypes.c_double),
+        ("gauss_abs", ctypes.c_double * 2), ("gauss_scale", ctypes.c_double * 2),
+        ("wind_abs", ctypes.c_int64 * 2), ("pq_count2", ctypes.c_int64),
+        ("L_p", ctypes.c_double), ("L_q", ctypes.c_double), ("L_pq", ctypes.c_double),
+        ("xi_p", ctypes.c_double), ("xi_q", ctypes.c_double), ("xi_pq", ctypes.c_double), ("xi_W", ctypes.c_double),
+        ("xi_lag", ctypes.c_double), ("f_total", ctypes.c_double), ("f_p", ctypes.c_double),
+        ("v2_lag", ctypes.c_double), ("v2_pq", ctypes.c_double), ("gauss_rel", ctypes.c_double * 2),
+        ("flags", ctypes.c_int32), ("pad", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        out = {}
+        for name, _ in self._fields_:
+            if name == "pad":
+                continue
+            v = getattr(self, name)
+            out[name] = tuple(v) if isinstance(v, ctypes.Array) else v
+        return out
+
+
+class MtsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_strerror(code)}: {msg}")
+        self.code = code
+
+
+_LIB = None
+
+
+def load():
+    """Load libmts.so (no fallback: the HIP library is the implementation)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2208_01525_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, pp = ctypes.c_void_p, ctypes.POINTER(Params)
+    L.mts_state_bytes.argtypes = [pp]
+    L.mts_state_bytes.restype = ctypes.c_size_t
+    L.mts_create.argtypes = [pp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.mts_destroy.argtypes = [vp]
+    L.mts_init_fields.argtypes = [vp, ctypes.c_uint64]
+    L.mts_step.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    L.mts_diagnostics.argtypes = [vp, ctypes.POINTER(Diag), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    L.mts_get_fields.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.mts_set_fields.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.mts_get_windings.argtypes = [vp, ctypes.POINTER(ctypes.c_int8)]
+    L.mts_get_cells.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8)]
+    L.mts_timing_enable.argtypes = [vp, ctypes.c_int32]
+    i64p, dp = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
+    L.mts_timing_read.argtypes = [vp, i64p, dp, i64p, dp, dp]
+    L.mts_last_error.argtypes = [vp]
+    L.mts_last_error.restype = ctypes.c_char_p
+    L.mts_strerror.argtypes = [ctypes.c_int]
+    L.mts_strerror.restype = ctypes.c_char_p
+    _LIB = L
+    return L
+
+
+def _strerror(code):
+    try:
+        return load().mts_strerror(code).decode()
+    except Exception:
+        return str(code)
+
+
+def make_params(nx, ny=None, nz=None, *, precision="fp32", dx=0.5, dt=0.1, lam=(2.0, 2.0), e=(1.0, 1.0),
+                sig=(1.0, 1.0), kappa=0.9, eta_ref=1.0, diag_every=0, overlap_radius=1):
+    p = Params()
+    p.nx = nx
+    p.ny = nx if ny is None else ny
+    p.nz = nx if nz is None else nz
+    p.precision = {"fp32": MTS_FP32, "fp64": MTS_FP64}[precision]
+    p.dx, p.dt = dx, dt
+    p.lambda_p, p.lambda_q = lam
+    p.e_p, p.e_q = e
+    p.sigma_p, p.sigma_q = sig
+    p.kappa, p.eta_ref = kappa, eta_ref
+    p.diag_every, p.overlap_radius = diag_every, overlap_radius
+    return p
+
+
+def state_bytes(params):
+    return load().mts_state_bytes(ctypes.byref(params))
+
+
+class Lattice:
+    """One periodic box on one GPU.  The device state buffer is a torch uint8
+    tensor of mts_state_bytes() bytes; all work goes to `stream` (default: the
+    current torch stream of `device`)."""
+
+    def __init__(self, params, device="cuda:0", stream=None):
+        import torch
+
+        self.L = load()
+        self.params = params
+        self.device = torch.device(device)
+        self.shape = (params.nz, params.ny, params.nx)
+        self.sites = params.nx * params.ny * params.nz
+        nbytes = state_bytes(params)
+        if nbytes == 0:
+            raise MtsError(MTS_EINVAL, "invalid parameters")
+        self.state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        rc = self.L.mts_create(ctypes.byref(params), ctypes.c_void_p(self.state.data_ptr()), nbytes,
+                               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        if rc != MTS_OK:
+            raise MtsError(rc, "mts_create failed")
+        self.ctx = ctx
+
+    def _check(self, rc):
+        if rc != MTS_OK:
+            raise MtsError(rc, self.L.mts_last_error(self.ctx).decode())
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.mts_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the C ABI, name for name --
+    def init_fields(self, seed):
+        self._check(self.L.mts_init_fields(self.ctx, ctypes.c_uint64(seed)))
+
+    def step(self, n, eta, era_m, s):
+        self._check(self.L.mts_step(self.ctx, int(n), float(eta), float(era_m), float(s)))
+
+    def diagnostics(self, max_records=8192, allow_nonfinite=False):
+        buf = (Diag * max_records)()
+        cnt = ctypes.c_int32()
+        rc = self.L.mts_diagnostics(self.ctx, buf, max_records, ctypes.byref(cnt))
+        if rc == MTS_ENONFINITE and allow_nonfinite:
+            rc = MTS_OK
+        self._check(rc)
+        return [buf[i].as_dict() for i in range(cnt.value)]
+
+    def get_fields(self):
+        out = np.empty((20,) + self.shape, dtype=np.float64)
+        self._check(self.L.mts_get_fields(self.ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def set_fields(self, host):
+        host = np.ascontiguousarray(host, dtype=np.float64)
+        assert host.shape == (20,) + self.shape
+        self._check(self.L.mts_set_fields(self.ctx, host.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def get_windings(self):
+        out = np.empty((6,) + self.shape, dtype=np.int8)
+        self._check(self.L.mts_get_windings(self.ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))))
+        return out
+
+    def get_cells(self):
+        out = np.empty((2,) + self.shape, dtype=np.uint8)
+        self._check(self.L.mts_get_cells(self.ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
+        return out
+
+    def timing_enable(self, on=True):
+        self._check(self.L.mts_timing_enable(self.ctx, 1 if on else 0))
+
+    def timing_read(self):
+        n0, n1 = ctypes.c_int64(), ctypes.c_int64()
+        t0, t1, t2 = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(self.L.mts_timing_read(self.ctx, ctypes.byref(n0), ctypes.byref(t0), ctypes.byref(n1),
+                                           ctypes.byref(t1), ctypes.byref(t2)))
+        return {"n_plain": n0.value, "ms_plain": t0.value, "n_diag": n1.value, "ms_diag": t1.value,
+                "ms_post": t2.value}

@@ -26,9 +26,12 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_SITE = {"fp32": 160, "fp64": 320}   # 20 reals read + 20 written per site-update
 
 
-def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0.5, s=1.0, eta_ref=128.0, seed=1):
+def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0.5, s=1.0, eta_ref=128.0, seed=1,
+            tile=None):
     params = P.make_params(n, precision=precision, eta_ref=eta_ref, diag_every=diag_every)
     lat = P.Lattice(params, device="cuda:0")
+    if tile is not None:
+        lat.set_tile(*tile)
     lat.init_fields(seed)
     lat.step(warmup, eta0, era_m, s)
     lat.diagnostics()
@@ -55,11 +58,48 @@ def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0
         "diag_post_ms": tm["ms_post"] / max(tm["n_diag"], 1),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "tile": lat.get_tile(),
         "last_record": {k: recs[-1][k] for k in ("eta", "xi_W", "xi_lag", "v2_lag", "f_total", "gauss_rel")}
         if recs else None,
     }
     lat.close()
     del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_batch(P, torch, steps, small=48, big=16, tune_steps=3):
+    """Ensemble of uneven boxes: `small` boxes of 128^3 and `big` of 256^3; box b has seed
+    1000 + b, m = 1/2 (b even) or 2/3 (b odd), s = 0 if b//2 is even else 1; all FP32, dx = 0.5,
+    dt = 0.1, kappa = 0.9, diagnostics every 10 steps, `steps` steps from eta = 1 with a = 1 at
+    the end, all advanced by one graph launch; tile shape from the autotuner."""
+    nb = small + big
+    eta_end = 1.0 + steps * 0.1
+    params = [P.make_params(128 if b < small else 256, precision="fp32", eta_ref=eta_end, diag_every=10)
+              for b in range(nb)]
+    bt = P.Batch(params)
+    ty, tz, tune_ms = bt.autotune(tune_steps)
+    bt.init_fields([1000 + b for b in range(nb)])
+    era = [0.5 if b % 2 == 0 else 2.0 / 3.0 for b in range(nb)]
+    sv = [0.0 if (b // 2) % 2 == 0 else 1.0 for b in range(nb)]
+    torch.cuda.synchronize()
+    bt.timing_read()
+    t0 = time.perf_counter()
+    bt.step(steps, [1.0] * nb, era, sv)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = bt.timing_read()
+    sites = sum(p.nx * p.ny * p.nz for p in params)
+    nrec = [len(bt.diagnostics(b)) for b in range(nb)]
+    achieved = BYTES_PER_SITE["fp32"] * sites * steps / (tm["ms"] * 1e-3) / 1e9
+    out = {"value": sites * steps / wall, "unit": "site-updates/s", "boxes": f"{small}x128^3 + {big}x256^3",
+           "sites": sites, "steps": steps, "ms_per_step": 1e3 * wall / steps, "graph_ms": tm["ms"],
+           "tile": [ty, tz], "autotune_ms_per_step": tune_ms, "records_per_box": min(nrec),
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "note": "whole graph time, diagnostic kernels included"}}
+    bt.close()
+    del bt
     torch.cuda.empty_cache()
     return out
 
@@ -80,6 +120,22 @@ def cpu_baseline():
             "sample": f"{n}^3 box, {steps} steps from eta=1 (m=1/2, s=1, diagnostics every 10), FP64, {dt:.1f} s"}
 
 
+def copy_probe(torch, gib=2, reps=5):
+    """A plain device-to-device copy of known size (`gib` GiB per copy), the
+    calibration for the HBM byte counters of the profiler."""
+    n = gib * (1 << 30)
+    src = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "reps": reps,
+                      "GB_per_s": 2 * n / dt / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +144,9 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--fp64-steps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=400)
+    ap.add_argument("--copy-probe", action="store_true", help="only time a plain copy (counter calibration)")
+    ap.add_argument("--tile", type=str, default=None, help="ty,tz of the update kernel (0,1: per-site kernel)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this implementation runs on one GPU only (the lattice is not sharded); "
@@ -98,13 +157,22 @@ def main():
 
     import paper_2208_01525_amd as P
 
-    fp32 = run_box(P, torch, args.n, "fp32", args.warmup, args.steps, diag_every=10)
+    if args.copy_probe:
+        copy_probe(torch)
+        return
+
+    tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
+    fp32 = run_box(P, torch, args.n, "fp32", args.warmup, args.steps, diag_every=10, tile=tile)
     print(f"fp32: {fp32['value']:.4g} site-updates/s, kernel {fp32['kernel_ms']:.3f} ms, "
           f"{fp32['roofline']['frac']:.3f} of HBM peak", file=sys.stderr, flush=True)
     fp64 = run_box(P, torch, args.n, "fp64", args.warmup, args.fp64_steps, diag_every=10) if args.fp64_steps else None
     if fp64:
         print(f"fp64: {fp64['value']:.4g} site-updates/s, kernel {fp64['kernel_ms']:.3f} ms, "
               f"{fp64['roofline']['frac']:.3f} of HBM peak", file=sys.stderr, flush=True)
+    batch = run_batch(P, torch, args.batch_steps) if args.batch_steps else None
+    if batch:
+        print(f"batch: {batch['value']:.4g} site-updates/s, {batch['roofline']['frac']:.3f} of HBM peak, "
+              f"tile {batch['tile']}", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline()
 
     line = {
@@ -127,11 +195,13 @@ def main():
         "roofline": fp32["roofline"],
         "cpu_baseline": cpu,
         "kernel_ms": fp32["kernel_ms"],
+        "tile": fp32["tile"],
         "diag_step_kernel_ms": fp32["diag_step_kernel_ms"],
         "diag_post_ms": fp32["diag_post_ms"],
         "fp64": {"value": fp64["value"], "unit": "site-updates/s", "steps": args.fp64_steps,
                  "ms_per_step": fp64["ms_per_step"], "kernel_ms": fp64["kernel_ms"],
                  "roofline": fp64["roofline"]} if fp64 else None,
+        "batch": batch,
         "last_record": fp32["last_record"],
     }
     print(json.dumps(line), flush=True)

@@ -171,6 +171,24 @@ int mts_get_windings(mts_ctx *ctx, int8_t *host);
  * uint8[2][S] (sector p, then q).  Synchronous. */
 int mts_get_cells(mts_ctx *ctx, uint8_t *host);
 
+/* Choose the update kernel.  ty in {4, 8, 12} selects the z-marching
+ * LDS-tiled kernel with tiles of 64 x ty sites and tz >= 1 planes per
+ * workgroup (default 8 x 32 in FP32, 4 x 32 in FP64); every tile shape
+ * gives bitwise identical
+ * results.  ty = 0 selects the one-thread-per-site kernel, which computes
+ * the plaquette sines directly and agrees with the tiled kernel to
+ * rounding.  Synchronises the stream.  EINVAL for other shapes. */
+int mts_set_tile(mts_ctx *ctx, int32_t ty, int32_t tz);
+int mts_get_tile(const mts_ctx *ctx, int32_t *ty, int32_t *tz);
+
+/* Autotuner: time `steps` plain steps of every supported tile shape
+ * (ty in {4, 8, 12} -- {4, 8} in FP64 -- by tz in {8, 16, 32, 64}) on this
+ * box with HIP events, keep the fastest, and report it (and its ms per
+ * step).  The choice changes speed only: results are bitwise identical for
+ * every shape.  Overwrites the lattice (it is left at seed-0 initial
+ * conditions): call it before mts_init_fields / mts_set_fields. */
+int mts_autotune(mts_ctx *ctx, int32_t steps, int32_t *ty, int32_t *tz, double *ms_per_step);
+
 /* Kernel timing with HIP events on the context's stream.  While enabled,
  * every launch of the update kernel is bracketed by events; the summary
  * returns the launch count and the summed event time in milliseconds of
@@ -180,6 +198,60 @@ int mts_get_cells(mts_ctx *ctx, uint8_t *host);
 int mts_timing_enable(mts_ctx *ctx, int32_t on);
 int mts_timing_read(mts_ctx *ctx, int64_t *n_plain, double *ms_plain, int64_t *n_diag, double *ms_diag,
                     double *ms_post);
+
+/* ------------------------------------------------------------ ensembles
+ * A batch advances several independent boxes (own size, couplings,
+ * eta_ref, era, s and seed; shared precision and diag_every) with one
+ * update kernel launch per step over all boxes' tiles, the whole n-step
+ * sequence of a mts_batch_step call captured into one HIP graph and
+ * launched once.  Box k behaves exactly as a single context with the same
+ * parameters and tile shape (bitwise identical fields). */
+typedef struct mts_batch mts_batch;
+
+/* Bytes of the device pool for nbox boxes: each box's mts_state_bytes()
+ * rounded up to 256, in box order.  0 if any box is invalid. */
+size_t mts_batch_state_bytes(const mts_params *boxes, int32_t nbox);
+
+/* Create a batch on the current device.  boxes[nbox] are copied; every box
+ * must share precision and diag_every (EINVAL otherwise).  dev_pool is a
+ * caller-owned device buffer of at least mts_batch_state_bytes() bytes,
+ * 256-byte aligned, borrowed for the batch's lifetime.  stream as for
+ * mts_create; the graphs run on an internal non-blocking stream of default
+ * priority that is joined to `stream` before and after every launch. */
+int mts_batch_create(const mts_params *boxes, int32_t nbox, void *dev_pool, size_t pool_bytes, void *stream,
+                     mts_batch **out);
+int mts_batch_destroy(mts_batch *b);
+int32_t mts_batch_size(const mts_batch *b);
+
+/* Random-phase initial conditions of every box, seeds[nbox] (host). */
+int mts_batch_init_fields(mts_batch *b, const uint64_t *seeds);
+
+/* Advance every box n steps in one graph launch.  Host arrays of nbox:
+ * eta0 (start time), era_m, s_before; s_after and eta_switch may be NULL.
+ * Box k uses beta = s_before[k] for steps with eta_j < eta_switch[k] and
+ * s_after[k] from then on (a core-growth phase followed by physical
+ * evolution, Sec. V).  Same checks and diagnostics as mts_step, per box. */
+int mts_batch_step(mts_batch *b, int32_t n, const double *eta0, const double *era_m, const double *s_before,
+                   const double *s_after, const double *eta_switch);
+
+/* Per-box access, as the single-context functions. */
+int mts_batch_diagnostics(mts_batch *b, int32_t box, mts_diag *out, int32_t max, int32_t *count);
+int mts_batch_get_fields(mts_batch *b, int32_t box, double *host);
+int mts_batch_set_fields(mts_batch *b, int32_t box, const double *host);
+
+/* Tile shape of the batched launch: one ty in {4, 8, 12} for all boxes and
+ * a tz[nbox] per box. */
+int mts_batch_set_tile(mts_batch *b, int32_t ty, const int32_t *tz);
+
+/* Summed HIP-event time (ms) of the graph launches and the steps they ran
+ * since the last read; synchronises. */
+int mts_batch_timing_read(mts_batch *b, int64_t *steps, double *ms);
+
+/* Autotuner of the batched launch (one ty and one tz for all boxes), as
+ * mts_autotune; overwrites every box. */
+int mts_batch_autotune(mts_batch *b, int32_t steps, int32_t *ty, int32_t *tz, double *ms_per_step);
+
+const char *mts_batch_last_error(const mts_batch *b);
 
 /* Text of the last error of ctx (never NULL). */
 const char *mts_last_error(const mts_ctx *ctx);

@@ -3,4 +3,4 @@
 The implementation is the HIP library libmts.so (C ABI in include/mts.h);
 `paper_2208_01525_amd.mts` is its thin Python binding.
 """
-from .mts import Lattice, MtsError, load, make_params, state_bytes  # noqa: F401
+from .mts import Batch, Lattice, MtsError, load, make_params, state_bytes  # noqa: F401

@@ -39,6 +39,7 @@ struct mts_ctx {
     double *partials = nullptr;  // [NSLOT][maxblk]
     uint32_t maxblk = 0;
     uint32_t *nblk_dev = nullptr;
+    TileShape tile{8, 32};       // ty = 0: per-site kernel
     uint8_t *wabs = nullptr;     // packed |W| per sector: [2][plane]
     uint8_t *cells = nullptr;    // cell values per sector: [2][plane]
     double *ring = nullptr;      // [RING_CAP][NSLOT]
@@ -202,6 +203,38 @@ struct TimedRegion {
     }
 };
 
+// Partials per slot: the update kernel's blocks for the integer-time sums,
+// the per-site grid for the post-step diagnostic kernels.
+hipError_t upload_nblk(mts_ctx *c) {
+    uint32_t nb[NSLOT];
+    const uint32_t step_blocks = c->tile.ty == 0 ? site_blocks(c->g) : tile_blocks(c->g, c->tile);
+    for (int q = 0; q < NSLOT; q++) nb[q] = q <= SL_GV ? step_blocks : (q <= SL_OV_Q ? site_blocks(c->g) : 0);
+    return hipMemcpy(c->nblk_dev, nb, sizeof(nb), hipMemcpyHostToDevice);
+}
+
+// Post-step diagnostic kernels of one box (windings + Gauss, cells, overlap,
+// reduce into the next ring slot) for the step from eta_j; fields at n are
+// in copy `cur`.  Host-side facts of the record are queued.
+template <typename T>
+hipError_t enqueue_diag_post(mts_ctx *c, const Book &b, double eta_j, double s, hipStream_t st) {
+    const mts_params &p = c->p;
+    Partials part{c->partials, c->maxblk};
+    double gcoef[2];
+    const double e2[2] = {p.e_p * p.e_p, p.e_q * p.e_q};
+    for (int q = 0; q < 2; q++) gcoef[q] = 2.0 * e2[q] * b.An * (1.0 + b.delta) / (1.0 + b.omega);
+    hipError_t e = launch_wind_gauss<T>(c->g, fields_of<T>(c, c->cur), moms_of<T>(c), (T)p.dx, gcoef, c->wabs,
+                                        (uint32_t)c->plane, nullptr, part, st);
+    if (e == hipSuccess) e = launch_cells(c->g, c->wabs, c->cells, (uint32_t)c->plane, st);
+    if (e == hipSuccess) e = launch_overlap(c->g, c->cells, (uint32_t)c->plane, p.overlap_radius, part, st);
+    double *rec = c->ring + (size_t)(c->produced % RING_CAP) * NSLOT;
+    if (e == hipSuccess) e = launch_reduce(part, c->nblk_dev, rec, st);
+    if (e != hipSuccess) return e;
+    c->meta.push_back({c->step_count, eta_j, b.a, s});
+    c->produced++;
+    c->have_cells = true;
+    return hipSuccess;
+}
+
 template <typename T>
 int do_step(mts_ctx *c, int32_t n, double eta, double era_m, double s) {
     const mts_params &p = c->p;
@@ -215,27 +248,42 @@ int do_step(mts_ctx *c, int32_t n, double eta, double era_m, double s) {
         Fields<T> in = fields_of<T>(c, c->cur), out = fields_of<T>(c, 1 - c->cur);
         {
             TimedRegion tr(c, diag ? 1 : 0);
-            hipError_t e = launch_step<T>(c->g, in, out, mom, coef, diag, part, c->stream);
+            hipError_t e = c->tile.ty == 0 ? launch_step<T>(c->g, in, out, mom, coef, diag, part, c->stream)
+                                           : launch_step_tile<T>(c->g, in, out, mom, coef, diag, part, c->tile,
+                                                                 c->stream);
             if (e != hipSuccess) return hipfail(c, e, "step kernel launch");
         }
         if (diag) {
             TimedRegion tr(c, 2);
-            double gcoef[2];
-            const double e2[2] = {p.e_p * p.e_p, p.e_q * p.e_q};
-            for (int q = 0; q < 2; q++) gcoef[q] = 2.0 * e2[q] * b.An * (1.0 + b.delta) / (1.0 + b.omega);
-            hipError_t e = launch_wind_gauss<T>(c->g, in, mom, (T)p.dx, gcoef, c->wabs, (uint32_t)c->plane, nullptr,
-                                                part, c->stream);
-            if (e == hipSuccess) e = launch_cells(c->g, c->wabs, c->cells, (uint32_t)c->plane, c->stream);
-            if (e == hipSuccess) e = launch_overlap(c->g, c->cells, (uint32_t)c->plane, p.overlap_radius, part, c->stream);
-            double *rec = c->ring + (size_t)(c->produced % RING_CAP) * NSLOT;
-            if (e == hipSuccess) e = launch_reduce(part, c->nblk_dev, rec, c->stream);
+            hipError_t e = enqueue_diag_post<T>(c, b, eta_j, s, c->stream);
             if (e != hipSuccess) return hipfail(c, e, "diagnostic kernel launch");
-            c->meta.push_back({c->step_count, eta_j, b.a, s});
-            c->produced++;
-            c->have_cells = true;
         }
         c->cur = 1 - c->cur;
         c->step_count++;
+    }
+    return MTS_OK;
+}
+
+// Argument checks of a run of n steps from eta (beta = s_before while
+// eta_j < eta_switch, s_after from then on), including the leapfrog
+// stability bound over the run's range of a^{2s}.
+int check_step(mts_ctx *c, int32_t n, double eta, double era_m, double s_before, double s_after, double eta_switch) {
+    if (n < 0) return fail(c, MTS_EINVAL, "n must be >= 0");
+    if (!(era_m >= 0.0 && era_m < 1.0)) return fail(c, MTS_EINVAL, "era_m must be in [0, 1)");
+    if (!std::isfinite(eta) || !std::isfinite(s_before) || !std::isfinite(s_after) || std::isnan(eta_switch))
+        return fail(c, MTS_EINVAL, "eta and s must be finite");
+    if (era_m > 0.0 && !(eta > 0.0)) return fail(c, MTS_EINVAL, "eta must be > 0 when era_m > 0");
+    if (n == 0) return MTS_OK;
+    const double eta_end = eta + (n - 1) * c->p.dt;
+    double Amax = 0.0;
+    for (double sv : {s_before, s_after})
+        for (double et : {eta, eta_end}) Amax = std::max(Amax, bookkeeping(c->p, et, era_m, sv).An);
+    const double k = c->p.dt, h = c->p.dx;
+    const double cfl = k * k * (12.0 / (h * h) + Amax * mu2_max(c->p));
+    if (!(cfl < 4.0)) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "unstable: dt^2 (12/h^2 + a^{2s}_max mu2_max) = %.4g >= 4", cfl);
+        return fail(c, MTS_EUNSTABLE, buf);
     }
     return MTS_OK;
 }
@@ -386,17 +434,15 @@ int mts_create(const mts_params *p, void *dev_state, size_t state_bytes, void *s
     c->plane = plane_of(*p);
     c->state = static_cast<char *>(dev_state);
     c->stream = static_cast<hipStream_t>(stream);
+    c->tile = p->precision == MTS_FP64 ? TileShape{4, 32} : TileShape{8, 32};
     c->maxblk = site_blocks(c->g);
+    for (int ty : {4, 8, 12}) c->maxblk = std::max(c->maxblk, tile_blocks(c->g, TileShape{ty, 1}));
     hipError_t e = hipMalloc(&c->partials, sizeof(double) * NSLOT * (size_t)c->maxblk);
     if (e == hipSuccess) e = hipMalloc(&c->nblk_dev, sizeof(uint32_t) * NSLOT);
     if (e == hipSuccess) e = hipMalloc(&c->wabs, 2 * c->plane);
     if (e == hipSuccess) e = hipMalloc(&c->cells, 2 * c->plane);
     if (e == hipSuccess) e = hipMalloc(&c->ring, sizeof(double) * NSLOT * RING_CAP);
-    if (e == hipSuccess) {
-        uint32_t nb[NSLOT];
-        for (int q = 0; q < NSLOT; q++) nb[q] = q < SL_OV_Q + 1 ? c->maxblk : 0;
-        e = hipMemcpy(c->nblk_dev, nb, sizeof(nb), hipMemcpyHostToDevice);
-    }
+    if (e == hipSuccess) e = upload_nblk(c);
     if (e != hipSuccess) {
         std::fprintf(stderr, "mts_create: scratch allocation failed: %s\n", hipGetErrorString(e));
         mts_destroy(c);
@@ -439,20 +485,8 @@ int mts_init_fields(mts_ctx *c, uint64_t seed) {
 
 int mts_step(mts_ctx *c, int32_t n, double eta, double era_m, double s) {
     if (!c) return MTS_EINVAL;
-    if (n < 0) return fail(c, MTS_EINVAL, "n must be >= 0");
-    if (!(era_m >= 0.0 && era_m < 1.0)) return fail(c, MTS_EINVAL, "era_m must be in [0, 1)");
-    if (!std::isfinite(eta) || !std::isfinite(s)) return fail(c, MTS_EINVAL, "eta and s must be finite");
-    if (era_m > 0.0 && !(eta > 0.0)) return fail(c, MTS_EINVAL, "eta must be > 0 when era_m > 0");
-    if (n == 0) return MTS_OK;
-    // leapfrog stability over the call's a-range (a^{2s} is monotone in eta)
-    const Book b0 = bookkeeping(c->p, eta, era_m, s), b1 = bookkeeping(c->p, eta + (n - 1) * c->p.dt, era_m, s);
-    const double Amax = std::max(b0.An, b1.An), k = c->p.dt, h = c->p.dx;
-    const double cfl = k * k * (12.0 / (h * h) + Amax * mu2_max(c->p));
-    if (!(cfl < 4.0)) {
-        char buf[160];
-        std::snprintf(buf, sizeof buf, "unstable: dt^2 (12/h^2 + a^{2s}_max mu2_max) = %.4g >= 4", cfl);
-        return fail(c, MTS_EUNSTABLE, buf);
-    }
+    const int rc = check_step(c, n, eta, era_m, s, s, INFINITY);
+    if (rc != MTS_OK || n == 0) return rc;
     return c->p.precision == MTS_FP64 ? do_step<double>(c, n, eta, era_m, s) : do_step<float>(c, n, eta, era_m, s);
 }
 
@@ -529,6 +563,65 @@ int mts_get_cells(mts_ctx *c, uint8_t *host) {
     return MTS_OK;
 }
 
+int mts_set_tile(mts_ctx *c, int32_t ty, int32_t tz) {
+    if (!c) return MTS_EINVAL;
+    const TileShape ts{ty, tz};
+    if (ty != 0 && !tile_supported(ts)) return fail(c, MTS_EINVAL, "tile: ty must be 0, 4, 8 or 12 and tz >= 1");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->tile = ts;
+    HIPCHK(c, upload_nblk(c));
+    return MTS_OK;
+}
+
+int mts_get_tile(const mts_ctx *c, int32_t *ty, int32_t *tz) {
+    if (!c || !ty || !tz) return MTS_EINVAL;
+    *ty = c->tile.ty;
+    *tz = c->tile.tz;
+    return MTS_OK;
+}
+
+int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, double *ms_out) {
+    if (!c || steps < 1) return MTS_EINVAL;
+    const std::vector<int> tys = c->p.precision == MTS_FP64 ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 12};
+    const int tzs[] = {8, 16, 32, 64};
+    const int32_t d = c->p.diag_every;
+    c->p.diag_every = 0;                       // time the plain update
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    double best = INFINITY;
+    TileShape pick = c->tile;
+    int rc = mts_init_fields(c, 0);
+    for (int ty : tys) {
+        for (int tz : tzs) {
+            if (rc != MTS_OK) break;
+            if (tz > 2 * c->p.nz && tz != 8) continue;
+            if ((rc = mts_set_tile(c, ty, tz)) != MTS_OK) break;
+            if ((rc = mts_step(c, 1, 1.0, 0.5, 1.0)) != MTS_OK) break;       // warm
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+            if ((rc = mts_step(c, steps, 1.1, 0.5, 1.0)) != MTS_OK) break;
+            HIPCHK(c, hipEventRecord(e1, c->stream));
+            HIPCHK(c, hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                pick = TileShape{ty, tz};
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->p.diag_every = d;
+    if (rc != MTS_OK) return rc;
+    if ((rc = mts_set_tile(c, pick.ty, pick.tz)) != MTS_OK) return rc;
+    if ((rc = mts_init_fields(c, 0)) != MTS_OK) return rc;
+    if (ty_out) *ty_out = pick.ty;
+    if (tz_out) *tz_out = pick.tz;
+    if (ms_out) *ms_out = best / steps;
+    return MTS_OK;
+}
+
 int mts_timing_enable(mts_ctx *c, int32_t on) {
     if (!c) return MTS_EINVAL;
     c->timing = on != 0;
@@ -574,5 +667,361 @@ const char *mts_strerror(int code) {
         default: return "MTS_E?";
     }
 }
+
+}  // extern "C"
+
+// ===================================================================== ensembles
+
+struct mts_batch {
+    std::vector<mts_ctx *> box;
+    int precision = MTS_FP32;
+    hipStream_t user = nullptr;      // caller's stream
+    hipStream_t stream = nullptr;    // internal stream the graphs are captured on and launched to
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
+    void *boxes_dev = nullptr;       // BatchBox<T>[nbox]
+    void *coef_dev = nullptr;        // StepCoef<T>[n][nbox]
+    size_t coef_cap = 0;             // bytes
+    int32_t ty = 8;
+    std::vector<int32_t> tz;
+    uint32_t nblk = 0;
+    hipGraphExec_t exec = nullptr;   // last launched graph (kept until the next call)
+    hipGraph_t graph = nullptr;
+    int64_t t_steps = 0;
+    double t_ms = 0.0;
+    bool t_pending = false;
+    int64_t t_pending_steps = 0;
+    std::string err;
+};
+
+namespace {
+
+int bfail(mts_batch *b, int code, const std::string &msg) {
+    if (b) b->err = msg;
+    return code;
+}
+
+#define BHIPCHK(bb, call)                                                                           \
+    do {                                                                                            \
+        hipError_t e_ = (call);                                                                     \
+        if (e_ != hipSuccess) return bfail(bb, MTS_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+template <typename T>
+int batch_upload_boxes(mts_batch *b) {
+    std::vector<BatchBox<T>> h(b->box.size());
+    uint32_t blk = 0;
+    for (size_t k = 0; k < b->box.size(); k++) {
+        mts_ctx *c = b->box[k];
+        BatchBox<T> &x = h[k];
+        x.g = c->g;
+        x.f[0] = fields_of<T>(c, 0);
+        x.f[1] = fields_of<T>(c, 1);
+        x.mom = moms_of<T>(c);
+        x.part = Partials{c->partials, c->maxblk};
+        x.tz = b->tz[k];
+        x.ntx = (c->g.nx + 63) / 64;
+        x.nty = (c->g.ny + b->ty - 1) / b->ty;
+        x.ntz = (c->g.nz + x.tz - 1) / x.tz;
+        x.blk0 = blk;
+        blk += (uint32_t)(x.ntx * x.nty * x.ntz);
+        c->tile = TileShape{b->ty, x.tz};
+        hipError_t e = upload_nblk(c);
+        if (e != hipSuccess) return bfail(b, MTS_EHIP, std::string("upload_nblk: ") + hipGetErrorString(e));
+    }
+    b->nblk = blk;
+    BHIPCHK(b, hipMemcpy(b->boxes_dev, h.data(), sizeof(BatchBox<T>) * h.size(), hipMemcpyHostToDevice));
+    return MTS_OK;
+}
+
+int batch_upload(mts_batch *b) {
+    return b->precision == MTS_FP64 ? batch_upload_boxes<double>(b) : batch_upload_boxes<float>(b);
+}
+
+void batch_release_graph(mts_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+void batch_collect_timing(mts_batch *b) {
+    if (!b->t_pending) return;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, b->ev_t0, b->ev_t1) == hipSuccess) {
+        b->t_ms += ms;
+        b->t_steps += b->t_pending_steps;
+    }
+    b->t_pending = false;
+}
+
+template <typename T>
+int batch_step_t(mts_batch *b, int32_t n, const double *eta0, const double *era_m, const double *s_before,
+                 const double *s_after, const double *eta_switch) {
+    const size_t nbox = b->box.size();
+    // per-box, per-step coefficients (FP64 bookkeeping, cast once)
+    const size_t need = sizeof(StepCoef<T>) * nbox * (size_t)n;
+    if (need > b->coef_cap) {
+        BHIPCHK(b, hipStreamSynchronize(b->stream));
+        batch_release_graph(b);
+        (void)hipFree(b->coef_dev);
+        b->coef_dev = nullptr;
+        b->coef_cap = 0;
+        BHIPCHK(b, hipMalloc(&b->coef_dev, need));
+        b->coef_cap = need;
+    }
+    std::vector<StepCoef<T>> tab(nbox * (size_t)n);
+    std::vector<std::vector<Book>> books(nbox, std::vector<Book>((size_t)n));
+    std::vector<std::vector<double>> svals(nbox, std::vector<double>((size_t)n));
+    for (size_t k = 0; k < nbox; k++) {
+        const mts_params &p = b->box[k]->p;
+        for (int32_t j = 0; j < n; j++) {
+            const double eta_j = eta0[k] + j * p.dt;
+            const double sw = eta_switch ? eta_switch[k] : INFINITY;
+            const double sj = eta_j < sw ? s_before[k] : (s_after ? s_after[k] : s_before[k]);
+            books[k][j] = bookkeeping(p, eta_j, era_m[k], sj);
+            svals[k][j] = sj;
+            tab[(size_t)j * nbox + k] = coefficients<T>(p, books[k][j], sj);
+        }
+    }
+    // the previous call's graph may still read the table: order the upload after it
+    BHIPCHK(b, hipMemcpyAsync(b->coef_dev, tab.data(), need, hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    batch_collect_timing(b);
+    batch_release_graph(b);
+
+    // join the caller's stream, capture all n steps, launch once, join back
+    BHIPCHK(b, hipEventRecord(b->ev_in, b->user));
+    BHIPCHK(b, hipStreamWaitEvent(b->stream, b->ev_in, 0));
+    BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    const int32_t d = b->box[0]->p.diag_every;
+    for (int32_t j = 0; j < n && err == hipSuccess; j++) {
+        mts_ctx *c0 = b->box[0];
+        const bool diag = d > 0 && (c0->step_count % d) == 0;
+        err = launch_step_tile_batch<T>(static_cast<const BatchBox<T> *>(b->boxes_dev), (int)nbox, b->nblk, c0->cur,
+                                        static_cast<const StepCoef<T> *>(b->coef_dev) + (size_t)j * nbox, diag, b->ty,
+                                        b->stream);
+        if (diag)
+            for (size_t k = 0; k < nbox && err == hipSuccess; k++)
+                err = enqueue_diag_post<T>(b->box[k], books[k][j], eta0[k] + j * b->box[k]->p.dt, svals[k][j],
+                                           b->stream);
+        for (mts_ctx *c : b->box) {
+            c->cur = 1 - c->cur;
+            c->step_count++;
+        }
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b->stream, &g);
+    if (err != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return bfail(b, MTS_EHIP, std::string("batch capture: ") + hipGetErrorString(err));
+    }
+    if (ec != hipSuccess) return bfail(b, MTS_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    b->graph = g;
+    BHIPCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    BHIPCHK(b, hipEventRecord(b->ev_t0, b->stream));
+    BHIPCHK(b, hipGraphLaunch(b->exec, b->stream));
+    BHIPCHK(b, hipEventRecord(b->ev_t1, b->stream));
+    b->t_pending = true;
+    b->t_pending_steps = n;
+    BHIPCHK(b, hipEventRecord(b->ev_out, b->stream));
+    BHIPCHK(b, hipStreamWaitEvent(b->user, b->ev_out, 0));
+    return MTS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mts_batch_state_bytes(const mts_params *boxes, int32_t nbox) {
+    if (!boxes || nbox <= 0) return 0;
+    size_t tot = 0;
+    for (int32_t k = 0; k < nbox; k++) {
+        const size_t v = mts_state_bytes(&boxes[k]);
+        if (v == 0) return 0;
+        tot += align256(v);
+    }
+    return tot;
+}
+
+int mts_batch_create(const mts_params *boxes, int32_t nbox, void *dev_pool, size_t pool_bytes, void *stream,
+                     mts_batch **out) {
+    if (!out) return MTS_EINVAL;
+    *out = nullptr;
+    if (!boxes || nbox <= 0) return MTS_EINVAL;
+    for (int32_t k = 1; k < nbox; k++)
+        if (boxes[k].precision != boxes[0].precision || boxes[k].diag_every != boxes[0].diag_every) {
+            std::fprintf(stderr, "mts_batch_create: every box must share precision and diag_every\n");
+            return MTS_EINVAL;
+        }
+    const size_t need = mts_batch_state_bytes(boxes, nbox);
+    if (need == 0) return MTS_EINVAL;
+    if (!dev_pool || (reinterpret_cast<uintptr_t>(dev_pool) & 255) != 0) return MTS_EINVAL;
+    if (pool_bytes < need) return MTS_ENOMEM;
+    mts_batch *b = new (std::nothrow) mts_batch;
+    if (!b) return MTS_ENOMEM;
+    b->precision = boxes[0].precision;
+    b->user = static_cast<hipStream_t>(stream);
+    b->ty = b->precision == MTS_FP64 ? 4 : 8;
+    size_t off = 0;
+    int rc = MTS_OK;
+    for (int32_t k = 0; k < nbox && rc == MTS_OK; k++) {
+        mts_ctx *c = nullptr;
+        const size_t sz = mts_state_bytes(&boxes[k]);
+        rc = mts_create(&boxes[k], static_cast<char *>(dev_pool) + off, sz, stream, &c);
+        if (rc == MTS_OK) {
+            b->box.push_back(c);
+            b->tz.push_back(32);
+        }
+        off += align256(sz);
+    }
+    hipError_t e = hipSuccess;
+    if (rc == MTS_OK) e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    for (hipEvent_t *ev : {&b->ev_in, &b->ev_out, &b->ev_t0, &b->ev_t1})
+        if (rc == MTS_OK && e == hipSuccess) e = hipEventCreate(ev);
+    if (rc == MTS_OK && e == hipSuccess) {
+        const size_t bb = (b->precision == MTS_FP64 ? sizeof(BatchBox<double>) : sizeof(BatchBox<float>)) * nbox;
+        e = hipMalloc(&b->boxes_dev, bb);
+    }
+    if (rc == MTS_OK && e != hipSuccess) rc = MTS_ENOMEM;
+    if (rc == MTS_OK) rc = batch_upload(b);
+    if (rc != MTS_OK) {
+        std::fprintf(stderr, "mts_batch_create: %s\n", b->err.c_str());
+        mts_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return MTS_OK;
+}
+
+int mts_batch_destroy(mts_batch *b) {
+    if (!b) return MTS_EINVAL;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    batch_release_graph(b);
+    for (mts_ctx *c : b->box) mts_destroy(c);
+    (void)hipFree(b->boxes_dev);
+    (void)hipFree(b->coef_dev);
+    for (hipEvent_t ev : {b->ev_in, b->ev_out, b->ev_t0, b->ev_t1})
+        if (ev) (void)hipEventDestroy(ev);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return MTS_OK;
+}
+
+int32_t mts_batch_size(const mts_batch *b) { return b ? (int32_t)b->box.size() : 0; }
+
+int mts_batch_init_fields(mts_batch *b, const uint64_t *seeds) {
+    if (!b || !seeds) return MTS_EINVAL;
+    for (size_t k = 0; k < b->box.size(); k++) {
+        const int rc = mts_init_fields(b->box[k], seeds[k]);
+        if (rc != MTS_OK) return bfail(b, rc, mts_last_error(b->box[k]));
+    }
+    return MTS_OK;
+}
+
+int mts_batch_step(mts_batch *b, int32_t n, const double *eta0, const double *era_m, const double *s_before,
+                   const double *s_after, const double *eta_switch) {
+    if (!b || !eta0 || !era_m || !s_before) return MTS_EINVAL;
+    for (size_t k = 0; k < b->box.size(); k++) {
+        mts_ctx *c = b->box[k];
+        const double sa = s_after ? s_after[k] : s_before[k];
+        const double sw = eta_switch ? eta_switch[k] : INFINITY;
+        const int rc = check_step(c, n, eta0[k], era_m[k], s_before[k], sa, sw);
+        if (rc != MTS_OK) return bfail(b, rc, "box " + std::to_string(k) + ": " + c->err);
+        if (c->cur != b->box[0]->cur || c->step_count != b->box[0]->step_count)
+            return bfail(b, MTS_EINVAL, "boxes must be initialised and stepped together");
+    }
+    if (n == 0) return MTS_OK;
+    return b->precision == MTS_FP64 ? batch_step_t<double>(b, n, eta0, era_m, s_before, s_after, eta_switch)
+                                    : batch_step_t<float>(b, n, eta0, era_m, s_before, s_after, eta_switch);
+}
+
+int mts_batch_diagnostics(mts_batch *b, int32_t box, mts_diag *out, int32_t max, int32_t *count) {
+    if (!b || box < 0 || box >= (int32_t)b->box.size()) return MTS_EINVAL;
+    return mts_diagnostics(b->box[box], out, max, count);
+}
+
+int mts_batch_get_fields(mts_batch *b, int32_t box, double *host) {
+    if (!b || box < 0 || box >= (int32_t)b->box.size()) return MTS_EINVAL;
+    return mts_get_fields(b->box[box], host);
+}
+
+int mts_batch_set_fields(mts_batch *b, int32_t box, const double *host) {
+    if (!b || box < 0 || box >= (int32_t)b->box.size()) return MTS_EINVAL;
+    return mts_set_fields(b->box[box], host);
+}
+
+int mts_batch_set_tile(mts_batch *b, int32_t ty, const int32_t *tz) {
+    if (!b || !tz) return MTS_EINVAL;
+    if (!tile_supported(TileShape{ty, 1})) return bfail(b, MTS_EINVAL, "ty must be 4, 8 or 12");
+    for (size_t k = 0; k < b->box.size(); k++)
+        if (tz[k] < 1) return bfail(b, MTS_EINVAL, "tz must be >= 1");
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->user));
+    b->ty = ty;
+    for (size_t k = 0; k < b->box.size(); k++) b->tz[k] = tz[k];
+    return batch_upload(b);
+}
+
+int mts_batch_timing_read(mts_batch *b, int64_t *steps, double *ms) {
+    if (!b) return MTS_EINVAL;
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    batch_collect_timing(b);
+    if (steps) *steps = b->t_steps;
+    if (ms) *ms = b->t_ms;
+    b->t_steps = 0;
+    b->t_ms = 0.0;
+    return MTS_OK;
+}
+
+int mts_batch_autotune(mts_batch *b, int32_t steps, int32_t *ty_out, int32_t *tz_out, double *ms_out) {
+    if (!b || steps < 1) return MTS_EINVAL;
+    const size_t nbox = b->box.size();
+    const std::vector<int> tys = b->precision == MTS_FP64 ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 12};
+    const int tzs[] = {8, 16, 32, 64};
+    std::vector<int32_t> d(nbox);
+    for (size_t k = 0; k < nbox; k++) {
+        d[k] = b->box[k]->p.diag_every;
+        b->box[k]->p.diag_every = 0;           // time the plain update
+    }
+    std::vector<uint64_t> seeds(nbox, 0);
+    std::vector<double> eta(nbox, 1.0), era(nbox, 0.5), sv(nbox, 1.0);
+    int rc = mts_batch_init_fields(b, seeds.data());
+    double best = INFINITY;
+    int pick_ty = b->ty, pick_tz = b->tz.empty() ? 32 : b->tz[0];
+    int nzmax = 0;
+    for (mts_ctx *c : b->box) nzmax = std::max(nzmax, c->p.nz);
+    for (int ty : tys)
+        for (int tz : tzs) {
+            if (rc != MTS_OK) break;
+            if (tz > 2 * nzmax && tz != 8) continue;
+            std::vector<int32_t> tzv(nbox, tz);
+            if ((rc = mts_batch_set_tile(b, ty, tzv.data())) != MTS_OK) break;
+            if ((rc = mts_batch_step(b, 1, eta.data(), era.data(), sv.data(), nullptr, nullptr)) != MTS_OK) break;
+            int64_t ns = 0;
+            double ms = 0;
+            if ((rc = mts_batch_timing_read(b, &ns, &ms)) != MTS_OK) break;
+            if ((rc = mts_batch_step(b, steps, eta.data(), era.data(), sv.data(), nullptr, nullptr)) != MTS_OK) break;
+            if ((rc = mts_batch_timing_read(b, &ns, &ms)) != MTS_OK) break;
+            if (ms < best) {
+                best = ms;
+                pick_ty = ty;
+                pick_tz = tz;
+            }
+        }
+    for (size_t k = 0; k < nbox; k++) b->box[k]->p.diag_every = d[k];
+    if (rc != MTS_OK) return rc;
+    std::vector<int32_t> tzv(nbox, pick_tz);
+    if ((rc = mts_batch_set_tile(b, pick_ty, tzv.data())) != MTS_OK) return rc;
+    if ((rc = mts_batch_init_fields(b, seeds.data())) != MTS_OK) return rc;
+    if (ty_out) *ty_out = pick_ty;
+    if (tz_out) *tz_out = pick_tz;
+    if (ms_out) *ms_out = best / steps;
+    return MTS_OK;
+}
+
+const char *mts_batch_last_error(const mts_batch *b) { return b ? b->err.c_str() : "null batch"; }
 
 }  // extern "C"

@@ -1,0 +1,93 @@
+// device.h -- device-side helpers shared by the gfx950 kernels of libmts:
+// complex arithmetic on interleaved (re, im) pairs, precision-generic math
+// wrappers, the link phasor and plaquette angle, and the deterministic
+// block reduction into FP64 partials.
+#pragma once
+#include <math.h>
+
+#include "kernels.h"
+
+namespace mts {
+
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {  // conj(a) * b
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ T imc(cx<T> a, cx<T> b) {  // Im(conj(a) * b)
+    return a.re * b.im - a.im * b.re;
+}
+template <typename T>
+__device__ __forceinline__ T norm2(cx<T> a) {
+    return a.re * a.re + a.im * a.im;
+}
+
+__device__ __forceinline__ void sincos_t(float x, float *s, float *c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sincos_t(double x, double *s, double *c) { sincos(x, s, c); }
+__device__ __forceinline__ float sin_t(float x) { return sinf(x); }
+__device__ __forceinline__ float cos_t(float x) { return cosf(x); }
+__device__ __forceinline__ double cos_t(double x) { return cos(x); }
+__device__ __forceinline__ double sin_t(double x) { return sin(x); }
+__device__ __forceinline__ float atan2_t(float y, float x) { return atan2f(y, x); }
+__device__ __forceinline__ double atan2_t(double y, double x) { return atan2(y, x); }
+__device__ __forceinline__ float rint_t(float x) { return rintf(x); }
+__device__ __forceinline__ double rint_t(double x) { return rint(x); }
+
+template <typename T>
+struct Pi;
+template <>
+struct Pi<float> {
+    static constexpr float v = 3.14159265358979323846f;
+};
+template <>
+struct Pi<double> {
+    static constexpr double v = 3.14159265358979323846;
+};
+
+// link phasor exp(-i h A)
+template <typename T>
+__device__ __forceinline__ cx<T> phasor(T hA) {
+    T s, c;
+    sincos_t(hA, &s, &c);
+    return {c, -s};
+}
+
+// plaquette angle from its four links, in the order
+// A_i(x) + A_j(x+i) - A_i(x+j) - A_j(x)
+template <typename T>
+__device__ __forceinline__ T plaq(T h, T a1, T a2, T a3, T a4) {
+    return h * (((a1 + a2) - a3) - a4);
+}
+
+// Deterministic block sum of NV doubles: wave64 shuffles, then the waves in
+// order through LDS; thread 0 writes partial[slot0 + v][blk].
+template <int NV, int NWAVES>
+__device__ __forceinline__ void block_sum_store(double (&v)[NV], Partials part, int slot0, uint32_t blk) {
+    __shared__ double red[NWAVES][NV];
+    const int lane = threadIdx.x + blockDim.x * threadIdx.y;
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        double t = v[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+        v[q] = t;
+    }
+    const int wave = lane >> 6;
+    if ((lane & 63) == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; q++) red[wave][q] = v[q];
+    }
+    __syncthreads();
+    if (lane < NV) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NWAVES; w++) t += red[w][lane];
+        part.base[(size_t)(slot0 + lane) * part.maxblk + blk] = t;
+    }
+}
+
+}  // namespace mts

@@ -77,6 +77,31 @@ template <typename T>
 hipError_t launch_step(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, const StepCoef<T> &c,
                        bool diag, Partials part, hipStream_t st);
 
+// The same step with the z-marching LDS-tiled kernel: a workgroup owns a
+// 64 x ty column of sites over tz planes; ty in {4, 8, 12}.
+struct TileShape {
+    int32_t ty, tz;
+};
+bool tile_supported(TileShape ts);
+uint32_t tile_blocks(const Geom &g, TileShape ts);
+template <typename T>
+hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, const StepCoef<T> &c,
+                            bool diag, Partials part, TileShape ts, hipStream_t st);
+
+// One box of an ensemble advanced by a single launch.
+template <typename T>
+struct BatchBox {
+    Geom g;
+    Fields<T> f[2];       // field copies 0 and 1
+    Moms<T> mom;
+    Partials part;        // this box's partials (box-local block index)
+    int32_t ntx, nty, ntz, tz;
+    uint32_t blk0;        // first block of this box in the launch
+};
+template <typename T>
+hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32_t nblk, int parity,
+                                  const StepCoef<T> *coef_dev, bool diag, int ty, hipStream_t st);
+
 // Windings of `f` (packed |W| per sector into wabs[2][plane] bytes, sum |W|
 // into partials) and the Gauss residual of (f, mom) with g_sigma.
 // If `signed_out` is non-null the signed windings go there as int8[6][plane]

@@ -1,0 +1,380 @@
+// step_tile.hip -- z-marching, LDS-tiled leapfrog step of the U(1)xU(1)
+// lattice update for gfx950 (Correia & Martins, arXiv:2208.01525, Sec. III).
+//
+// A workgroup owns a 64 x TY column of sites and walks it through TZ planes.
+// Waves 0..TY-1 hold the 64-wide rows of the tile, wave TY the row below it,
+// wave TY+1 the row above it, wave TY+2 the two halo columns (with corners).
+// Per plane every thread loads its site's fields once, evaluates its three
+// link phasors U_i = exp(-i h A_i) per sector (one sincos each) and stages
+// phi and U in LDS; then it forms its own three plaquette phasors
+//   P_ij(x) = U_i(x) U_j(x+i) conj(U_i(x+j)) conj(U_j(x)) = exp(-i theta_ij(x)),
+// so sin theta = -Im P and cos theta = Re P without further transcendental
+// work, and stages the sines.  The z-neighbours (phi(z-1), U_z(z-1), the
+// sines of plane z-1, and phi, U_x, U_y of plane z+1) stay in registers.
+// Interior threads then apply the kick and drift exactly as the per-site
+// kernel does.  Each field value is read from HBM once per step (halo
+// re-reads come from L2); momenta and fields are read and written once.
+//
+// Workgroups are numbered so that each XCD (workgroups are dealt round-robin
+// to the 8 XCDs) processes one contiguous run of tiles, keeping the halo
+// rows shared by neighbouring tiles inside one L2.
+#include "device.h"
+#include "kernels.h"
+
+namespace mts {
+
+namespace {
+
+constexpr int NXCD = 8;
+constexpr int LW = 66;    // LDS row width: 64 + two halo columns
+
+__device__ __forceinline__ int wrapi(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// LDS quantities per sector
+enum Q { Q_FR, Q_FI, Q_UXR, Q_UXI, Q_UYR, Q_UYI, Q_UZR, Q_UZI, Q_SXY, Q_SXZ, Q_SYZ, NQ };
+
+template <typename T, int TY>
+struct Lds {
+    T v[2][NQ][(TY + 2) * LW];
+};
+
+template <typename T, int TY>
+__device__ __forceinline__ cx<T> ldc(const Lds<T, TY> &L, int sec, int q, int i) {
+    return cx<T>{L.v[sec][q][i], L.v[sec][q + 1][i]};
+}
+
+}  // namespace
+
+// XCD-contiguous numbering of a 1-D grid of nblk workgroups: the blocks the
+// hardware deals to XCD k (k, k + 8, ...) become one contiguous run.
+__device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t nblk) {
+    const uint32_t xcd = b % NXCD, slot = b / NXCD;
+    const uint32_t per = nblk / NXCD, extra = nblk % NXCD;
+    return xcd * per + min(xcd, extra) + slot;
+}
+
+// One tile (64 x TY columns, planes [Z0, Z0 + TZ)) of one box; accumulates the
+// integer-time sums of its interior sites into acc when DIAG.
+template <typename T, bool DIAG, int TY>
+__device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, const Fields<T> &out,
+                                          const Moms<T> &mom, const StepCoef<T> &c, int X0, int Y0, int Z0, int TZ,
+                                          Lds<T, TY> &L, double (&acc)[6]) {
+    constexpr int R = TY + 2;
+
+    // ---- which site of the tile this thread holds
+    const int lx = threadIdx.x, w = threadIdx.y;
+    int row, col;
+    bool owner = true;
+    if (w < TY) {
+        row = w + 1;
+        col = lx + 1;
+    } else if (w == TY) {
+        row = 0;
+        col = lx + 1;
+    } else if (w == TY + 1) {
+        row = R - 1;
+        col = lx + 1;
+    } else if (lx < R) {
+        row = lx;
+        col = 0;
+    } else if (lx < 2 * R) {
+        row = lx - R;
+        col = LW - 1;
+    } else {
+        row = 0;
+        col = 0;
+        owner = false;
+    }
+    const int gx = X0 - 1 + col, gy = Y0 - 1 + row;
+    const int x = wrapi(gx, g.nx), y = wrapi(gy, g.ny);
+    const bool interior = w < TY && gx < g.nx && gy < g.ny;
+    const uint32_t colidx = (uint32_t)x + (uint32_t)g.nx * (uint32_t)y;
+    const int li = row * LW + col;
+    const int lxp = row * LW + min(col + 1, LW - 1), lyp = min(row + 1, R - 1) * LW + col;
+    const int lxm = row * LW + max(col - 1, 0), lym = max(row - 1, 0) * LW + col;
+
+    const int zbeg = Z0, zend = min(Z0 + TZ, g.nz);
+
+    // registers: plane z (cur), z+1 (nxt), z-1 (prv)
+    cx<T> cf[2], nf[2], pf[2];
+    T cA[2][3], nA[2][3];
+    cx<T> cU[2][3], nU[2][3], pUz[2];
+    T psxz[2], psyz[2];
+    auto load_plane = [&](int zz, cx<T> (&f)[2], T (&A)[2][3], cx<T> (&U)[2][3]) {
+        const uint32_t s = colidx + g.nxy * (uint32_t)zz;
+#pragma unroll
+        for (int sec = 0; sec < 2; sec++) {
+            f[sec] = in.phi[sec][s];
+#pragma unroll
+            for (int i = 0; i < 3; i++) A[sec][i] = in.A[sec][i][s];
+        }
+#pragma unroll
+        for (int sec = 0; sec < 2; sec++)
+#pragma unroll
+            for (int i = 0; i < 3; i++) U[sec][i] = phasor<T>(c.h * A[sec][i]);
+    };
+
+    load_plane(wrapi(zbeg - 1, g.nz), cf, cA, cU);
+
+    for (int z = zbeg - 1; z < zend; z++) {
+        const bool upd = interior && z >= zbeg;
+        const int zz = wrapi(z, g.nz);
+        const uint32_t s = colidx + g.nxy * (uint32_t)zz;
+        load_plane(wrapi(z + 1, g.nz), nf, nA, nU);
+        cx<T> p0[2];
+        T e0[2][3];
+        if (upd) {
+#pragma unroll
+            for (int sec = 0; sec < 2; sec++) {
+                p0[sec] = mom.pi[sec][s];
+#pragma unroll
+                for (int i = 0; i < 3; i++) e0[sec][i] = mom.E[sec][i][s];
+            }
+        }
+
+        // stage phi and U of plane z
+        if (owner) {
+#pragma unroll
+            for (int sec = 0; sec < 2; sec++) {
+                L.v[sec][Q_FR][li] = cf[sec].re;
+                L.v[sec][Q_FI][li] = cf[sec].im;
+#pragma unroll
+                for (int i = 0; i < 3; i++) {
+                    L.v[sec][Q_UXR + 2 * i][li] = cU[sec][i].re;
+                    L.v[sec][Q_UXI + 2 * i][li] = cU[sec][i].im;
+                }
+            }
+        }
+        __syncthreads();
+
+        // own plaquette phasors of plane z: P = U_i(x) U_j(x+i) conj(U_i(x+j)) conj(U_j(x))
+        T sn[2][3], cs[2][3];
+#pragma unroll
+        for (int sec = 0; sec < 2; sec++) {
+            const cx<T> uy_px = ldc(L, sec, Q_UYR, lxp), ux_py = ldc(L, sec, Q_UXR, lyp);
+            const cx<T> uz_px = ldc(L, sec, Q_UZR, lxp), uz_py = ldc(L, sec, Q_UZR, lyp);
+            const cx<T> ux = cU[sec][0], uy = cU[sec][1], uz = cU[sec][2];
+            // xy: U_x(x) U_y(x+x) conj(U_x(x+y) U_y(x))
+            const cx<T> axy = cmul(ux, uy_px), bxy = cmul(ux_py, uy);
+            const cx<T> Pxy = cmulc(bxy, axy);     // conj(b) a
+            const cx<T> axz = cmul(ux, uz_px), bxz = cmul(nU[sec][0], uz);
+            const cx<T> Pxz = cmulc(bxz, axz);
+            const cx<T> ayz = cmul(uy, uz_py), byz = cmul(nU[sec][1], uz);
+            const cx<T> Pyz = cmulc(byz, ayz);
+            sn[sec][0] = -Pxy.im;
+            sn[sec][1] = -Pxz.im;
+            sn[sec][2] = -Pyz.im;
+            cs[sec][0] = Pxy.re;
+            cs[sec][1] = Pxz.re;
+            cs[sec][2] = Pyz.re;
+            if (owner) {
+                L.v[sec][Q_SXY][li] = sn[sec][0];
+                L.v[sec][Q_SXZ][li] = sn[sec][1];
+                L.v[sec][Q_SYZ][li] = sn[sec][2];
+            }
+        }
+        __syncthreads();
+
+        if (upd) {
+            T Kd = 0, Gd = 0, Kg = 0, Bg = 0, mod2[2] = {0, 0};
+#pragma unroll
+            for (int sec = 0; sec < 2; sec++) {
+                const cx<T> f = cf[sec], o = cf[1 - sec];
+                const cx<T> fxp = ldc(L, sec, Q_FR, lxp), fxm = ldc(L, sec, Q_FR, lxm);
+                const cx<T> fyp = ldc(L, sec, Q_FR, lyp), fym = ldc(L, sec, Q_FR, lym);
+                const cx<T> fzp = nf[sec], fzm = pf[sec];
+                const cx<T> ux = cU[sec][0], uy = cU[sec][1], uz = cU[sec][2];
+                const cx<T> ux_m = ldc(L, sec, Q_UXR, lxm), uy_m = ldc(L, sec, Q_UYR, lym), uz_m = pUz[sec];
+                const cx<T> wx = cmul(ux, fxp), wy = cmul(uy, fyp), wz = cmul(uz, fzp);
+                const cx<T> vx = cmulc(ux_m, fxm), vy = cmulc(uy_m, fym), vz = cmulc(uz_m, fzm);
+
+                cx<T> lap;
+                lap.re = (((wx.re + vx.re) + (wy.re + vy.re)) + (wz.re + vz.re)) - T(6) * f.re;
+                lap.im = (((wx.im + vx.im) + (wy.im + vy.im)) + (wz.im + vz.im)) - T(6) * f.im;
+                const T m2 = norm2(f), o2 = norm2(o);
+                const T br = c.lamh[sec] * (m2 - c.sig2[sec]) - c.kap * (o2 - c.sig2[1 - sec]);
+                cx<T> F;
+                F.re = c.inv_h2 * lap.re - br * f.re;
+                F.im = c.inv_h2 * lap.im - br * f.im;
+
+                cx<T> p1;
+                p1.re = c.cpi * p0[sec].re + c.kpi * F.re;
+                p1.im = c.cpi * p0[sec].im + c.kpi * F.im;
+                mom.pi[sec][s] = p1;
+                cx<T> fn;
+                fn.re = f.re + c.k * p1.re;
+                fn.im = f.im + c.k * p1.im;
+                out.phi[sec][s] = fn;
+
+                const T sxy = sn[sec][0], sxz = sn[sec][1], syz = sn[sec][2];
+                const T sxy_my = L.v[sec][Q_SXY][lym], sxy_mx = L.v[sec][Q_SXY][lxm];
+                const T sxz_mx = L.v[sec][Q_SXZ][lxm], syz_my = L.v[sec][Q_SYZ][lym];
+                const T sxz_mz = psxz[sec], syz_mz = psyz[sec];
+                const T Mx = -c.inv_h3 * ((sxy - sxy_my) + (sxz - sxz_mz));
+                const T My = -c.inv_h3 * ((sxy_mx - sxy) + (syz - syz_mz));
+                const T Mz = -c.inv_h3 * ((sxz_mx - sxz) + (syz_my - syz));
+                const T Jx = c.cur[sec] * imc(f, wx), Jy = c.cur[sec] * imc(f, wy), Jz = c.cur[sec] * imc(f, wz);
+                const T e1x = c.cE * e0[sec][0] + c.kE * (Mx + Jx);
+                const T e1y = c.cE * e0[sec][1] + c.kE * (My + Jy);
+                const T e1z = c.cE * e0[sec][2] + c.kE * (Mz + Jz);
+                mom.E[sec][0][s] = e1x;
+                mom.E[sec][1][s] = e1y;
+                mom.E[sec][2][s] = e1z;
+                out.A[sec][0][s] = cA[sec][0] + c.k * e1x;
+                out.A[sec][1][s] = cA[sec][1] + c.k * e1y;
+                out.A[sec][2][s] = cA[sec][2] + c.k * e1z;
+
+                if constexpr (DIAG) {
+                    cx<T> pb;
+                    pb.re = T(0.5) * (p0[sec].re + p1.re);
+                    pb.im = T(0.5) * (p0[sec].im + p1.im);
+                    Kd += norm2(pb);
+                    cx<T> dx_, dy_, dz_;
+                    dx_.re = wx.re - f.re; dx_.im = wx.im - f.im;
+                    dy_.re = wy.re - f.re; dy_.im = wy.im - f.im;
+                    dz_.re = wz.re - f.re; dz_.im = wz.im - f.im;
+                    Gd += c.inv_h2 * ((norm2(dx_) + norm2(dy_)) + norm2(dz_));
+                    const T ebx = T(0.5) * (e0[sec][0] + e1x), eby = T(0.5) * (e0[sec][1] + e1y),
+                            ebz = T(0.5) * (e0[sec][2] + e1z);
+                    Kg += c.inv_2e2[sec] * ((ebx * ebx + eby * eby) + ebz * ebz);
+                    Bg += c.inv_e2h4[sec] * (((T(1) - cs[sec][0]) + (T(1) - cs[sec][1])) + (T(1) - cs[sec][2]));
+                    mod2[sec] = m2;
+                }
+            }
+            if constexpr (DIAG) {
+                const T dp = mod2[0] - c.sig2[0], dq = mod2[1] - c.sig2[1];
+                const T Vint = c.kap0 * dp * dq;
+                const T V = (c.lam4[0] * dp * dp + c.lam4[1] * dq * dq) - Vint;
+                const T eps = (Kd + Gd) + c.am2s * (Kg + Bg) + c.a2s * V;
+                const T lag = (Kd - Gd) + c.am2s * (Kg - Bg) - c.a2s * V;
+                const double K = Kd, G = Gd, Lg = lag, Vi = Vint;
+                acc[0] += (double)eps;
+                acc[1] += Lg;
+                acc[2] += K * Lg;
+                acc[3] += G * Lg;
+                acc[4] += K * Vi;
+                acc[5] += G * Vi;
+            }
+        }
+        __syncthreads();   // LDS of plane z is reused by plane z+1
+
+        // rotate registers
+#pragma unroll
+        for (int sec = 0; sec < 2; sec++) {
+            pf[sec] = cf[sec];
+            pUz[sec] = cU[sec][2];
+            psxz[sec] = sn[sec][1];
+            psyz[sec] = sn[sec][2];
+            cf[sec] = nf[sec];
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                cA[sec][i] = nA[sec][i];
+                cU[sec][i] = nU[sec][i];
+            }
+        }
+    }
+}
+
+template <typename T, bool DIAG, int TY>
+__global__ __launch_bounds__(64 * (TY + 3)) void step_tile_kernel(Geom g, Fields<T> in, Fields<T> out, Moms<T> mom,
+                                                                  StepCoef<T> c, Partials part, int TZ, int ntx,
+                                                                  int nty, int ntz) {
+    __shared__ Lds<T, TY> L;
+    const uint32_t t = xcd_order(blockIdx.x, (uint32_t)(ntx * nty * ntz));
+    const int tx = t % ntx, ty_ = (t / ntx) % nty, tz = t / (ntx * nty);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    tile_step<T, DIAG, TY>(g, in, out, mom, c, tx * 64, ty_ * TY, tz * TZ, TZ, L, acc);
+    if constexpr (DIAG) block_sum_store<6, TY + 3>(acc, part, SL_EPS, t);
+}
+
+// Ensemble of boxes in one launch: the blocks of box k are [blk0[k], blk0[k+1])
+// of the XCD-ordered grid; each box has its own fields, coefficients and
+// partials (indexed by the box-local block).
+template <typename T, bool DIAG, int TY>
+__global__ __launch_bounds__(64 * (TY + 3)) void step_tile_batch_kernel(const BatchBox<T> *boxes, int nbox,
+                                                                        int parity, const StepCoef<T> *coef,
+                                                                        uint32_t nblk) {
+    __shared__ Lds<T, TY> L;
+    const uint32_t t = xcd_order(blockIdx.x, nblk);
+    int lo = 0, hi = nbox - 1;             // last box with blk0 <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (boxes[mid].blk0 <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchBox<T> &bx = boxes[lo];
+    const uint32_t lt = t - bx.blk0;
+    const int tx = lt % bx.ntx, ty_ = (lt / bx.ntx) % bx.nty, tz = lt / (bx.ntx * bx.nty);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    tile_step<T, DIAG, TY>(bx.g, bx.f[parity], bx.f[1 - parity], bx.mom, coef[lo], tx * 64, ty_ * TY, tz * bx.tz,
+                           bx.tz, L, acc);
+    if constexpr (DIAG) block_sum_store<6, TY + 3>(acc, bx.part, SL_EPS, lt);
+}
+
+bool tile_supported(TileShape ts) { return (ts.ty == 4 || ts.ty == 8 || ts.ty == 12) && ts.tz >= 1; }
+
+uint32_t tile_blocks(const Geom &g, TileShape ts) {
+    const uint32_t ntx = (g.nx + 63) / 64, nty = (g.ny + ts.ty - 1) / ts.ty, ntz = (g.nz + ts.tz - 1) / ts.tz;
+    return ntx * nty * ntz;
+}
+
+template <typename T, int TY>
+static hipError_t launch_ty(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, const StepCoef<T> &c, bool diag,
+                            Partials part, int tz, hipStream_t st) {
+    const int ntx = (g.nx + 63) / 64, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + tz - 1) / tz;
+    dim3 block(64, TY + 3, 1);
+    dim3 grid((unsigned)(ntx * nty * ntz), 1, 1);
+    if (diag)
+        step_tile_kernel<T, true, TY><<<grid, block, 0, st>>>(g, in, out, mom, c, part, tz, ntx, nty, ntz);
+    else
+        step_tile_kernel<T, false, TY><<<grid, block, 0, st>>>(g, in, out, mom, c, part, tz, ntx, nty, ntz);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, const StepCoef<T> &c, bool diag,
+                            Partials part, TileShape ts, hipStream_t st) {
+    switch (ts.ty) {
+        case 4: return launch_ty<T, 4>(g, in, out, mom, c, diag, part, ts.tz, st);
+        case 8: return launch_ty<T, 8>(g, in, out, mom, c, diag, part, ts.tz, st);
+        case 12: return launch_ty<T, 12>(g, in, out, mom, c, diag, part, ts.tz, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32_t nblk, int parity,
+                                  const StepCoef<T> *coef_dev, bool diag, int ty, hipStream_t st) {
+    dim3 grid(nblk, 1, 1);
+#define MTS_BATCH_CASE(TYV)                                                                                  \
+    case TYV: {                                                                                              \
+        dim3 block(64, TYV + 3, 1);                                                                          \
+        if (diag)                                                                                            \
+            step_tile_batch_kernel<T, true, TYV><<<grid, block, 0, st>>>(boxes_dev, nbox, parity, coef_dev, nblk); \
+        else                                                                                                 \
+            step_tile_batch_kernel<T, false, TYV><<<grid, block, 0, st>>>(boxes_dev, nbox, parity, coef_dev, nblk); \
+        return hipGetLastError();                                                                            \
+    }
+    switch (ty) {
+        MTS_BATCH_CASE(4)
+        MTS_BATCH_CASE(8)
+        MTS_BATCH_CASE(12)
+        default: return hipErrorInvalidValue;
+    }
+#undef MTS_BATCH_CASE
+}
+
+template hipError_t launch_step_tile_batch<float>(const BatchBox<float> *, int, uint32_t, int, const StepCoef<float> *,
+                                                  bool, int, hipStream_t);
+template hipError_t launch_step_tile_batch<double>(const BatchBox<double> *, int, uint32_t, int,
+                                                   const StepCoef<double> *, bool, int, hipStream_t);
+
+template hipError_t launch_step_tile<float>(const Geom &, Fields<float>, Fields<float>, Moms<float>,
+                                            const StepCoef<float> &, bool, Partials, TileShape, hipStream_t);
+template hipError_t launch_step_tile<double>(const Geom &, Fields<double>, Fields<double>, Moms<double>,
+                                             const StepCoef<double> &, bool, Partials, TileShape, hipStream_t);
+
+}  // namespace mts

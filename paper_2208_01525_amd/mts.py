@@ -18,8 +18,12 @@ MTS_OK, MTS_EINVAL, MTS_EUNSTABLE, MTS_ENOMEM, MTS_EHIP, MTS_ENONFINITE = 0, -1,
 MTS_FP32, MTS_FP64 = 1, 2
 
 EXPORTS = ("mts_state_bytes", "mts_create", "mts_destroy", "mts_init_fields", "mts_step", "mts_diagnostics",
-           "mts_get_fields", "mts_set_fields", "mts_get_windings", "mts_get_cells", "mts_timing_enable",
-           "mts_timing_read", "mts_last_error", "mts_strerror")
+           "mts_get_fields", "mts_set_fields", "mts_get_windings", "mts_get_cells", "mts_set_tile", "mts_get_tile", "mts_autotune", "mts_timing_enable",
+           "mts_timing_read", "mts_last_error", "mts_strerror",
+           "mts_batch_state_bytes", "mts_batch_create", "mts_batch_destroy", "mts_batch_size",
+           "mts_batch_init_fields", "mts_batch_step", "mts_batch_diagnostics", "mts_batch_get_fields",
+           "mts_batch_set_fields", "mts_batch_set_tile", "mts_batch_timing_read", "mts_batch_autotune",
+           "mts_batch_last_error")
 
 
 class Params(ctypes.Structure):
@@ -88,6 +92,11 @@ def load():
     L.mts_set_fields.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.mts_get_windings.argtypes = [vp, ctypes.POINTER(ctypes.c_int8)]
     L.mts_get_cells.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8)]
+    L.mts_set_tile.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.mts_get_tile.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    L.mts_autotune.argtypes = [vp, ctypes.c_int32, i32p, i32p, ctypes.POINTER(ctypes.c_double)]
+    L.mts_batch_autotune.argtypes = [vp, ctypes.c_int32, i32p, i32p, ctypes.POINTER(ctypes.c_double)]
     L.mts_timing_enable.argtypes = [vp, ctypes.c_int32]
     i64p, dp = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
     L.mts_timing_read.argtypes = [vp, i64p, dp, i64p, dp, dp]
@@ -95,6 +104,23 @@ def load():
     L.mts_last_error.restype = ctypes.c_char_p
     L.mts_strerror.argtypes = [ctypes.c_int]
     L.mts_strerror.restype = ctypes.c_char_p
+    dpp = ctypes.POINTER(ctypes.c_double)
+    L.mts_batch_state_bytes.argtypes = [pp, ctypes.c_int32]
+    L.mts_batch_state_bytes.restype = ctypes.c_size_t
+    L.mts_batch_create.argtypes = [pp, ctypes.c_int32, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.mts_batch_destroy.argtypes = [vp]
+    L.mts_batch_size.argtypes = [vp]
+    L.mts_batch_size.restype = ctypes.c_int32
+    L.mts_batch_init_fields.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+    L.mts_batch_step.argtypes = [vp, ctypes.c_int32, dpp, dpp, dpp, dpp, dpp]
+    L.mts_batch_diagnostics.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(Diag), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32)]
+    L.mts_batch_get_fields.argtypes = [vp, ctypes.c_int32, dpp]
+    L.mts_batch_set_fields.argtypes = [vp, ctypes.c_int32, dpp]
+    L.mts_batch_set_tile.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    L.mts_batch_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), dpp]
+    L.mts_batch_last_error.argtypes = [vp]
+    L.mts_batch_last_error.restype = ctypes.c_char_p
     _LIB = L
     return L
 
@@ -202,6 +228,19 @@ class Lattice:
         self._check(self.L.mts_get_cells(self.ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))
         return out
 
+    def set_tile(self, ty, tz):
+        self._check(self.L.mts_set_tile(self.ctx, int(ty), int(tz)))
+
+    def get_tile(self):
+        ty, tz = ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.L.mts_get_tile(self.ctx, ctypes.byref(ty), ctypes.byref(tz)))
+        return ty.value, tz.value
+
+    def autotune(self, steps=5):
+        ty, tz, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        self._check(self.L.mts_autotune(self.ctx, int(steps), ctypes.byref(ty), ctypes.byref(tz), ctypes.byref(ms)))
+        return ty.value, tz.value, ms.value
+
     def timing_enable(self, on=True):
         self._check(self.L.mts_timing_enable(self.ctx, 1 if on else 0))
 
@@ -212,3 +251,91 @@ class Lattice:
                                            ctypes.byref(t1), ctypes.byref(t2)))
         return {"n_plain": n0.value, "ms_plain": t0.value, "n_diag": n1.value, "ms_diag": t1.value,
                 "ms_post": t2.value}
+
+
+def _darr(values, n):
+    if values is None:
+        return None
+    v = [float(x) for x in (values if hasattr(values, "__len__") else [values] * n)]
+    assert len(v) == n
+    return (ctypes.c_double * n)(*v)
+
+
+class Batch:
+    """An ensemble of independent boxes advanced together (one update launch per
+    step over all boxes, each n-step call captured into one HIP graph)."""
+
+    def __init__(self, params_list, device="cuda:0", stream=None):
+        import torch
+
+        self.L = load()
+        self.n = len(params_list)
+        arr = (Params * self.n)(*params_list)
+        self.params = list(params_list)
+        nbytes = self.L.mts_batch_state_bytes(arr, self.n)
+        if nbytes == 0:
+            raise MtsError(MTS_EINVAL, "invalid box parameters")
+        self.device = torch.device(device)
+        self.pool = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        b = ctypes.c_void_p()
+        rc = self.L.mts_batch_create(arr, self.n, ctypes.c_void_p(self.pool.data_ptr()), nbytes,
+                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(b))
+        if rc != MTS_OK:
+            raise MtsError(rc, "mts_batch_create failed")
+        self.b = b
+
+    def _check(self, rc):
+        if rc != MTS_OK:
+            raise MtsError(rc, self.L.mts_batch_last_error(self.b).decode())
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.L.mts_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_fields(self, seeds):
+        arr = (ctypes.c_uint64 * self.n)(*[int(s) for s in seeds])
+        self._check(self.L.mts_batch_init_fields(self.b, arr))
+
+    def step(self, n, eta0, era_m, s_before, s_after=None, eta_switch=None):
+        self._check(self.L.mts_batch_step(self.b, int(n), _darr(eta0, self.n), _darr(era_m, self.n),
+                                          _darr(s_before, self.n), _darr(s_after, self.n),
+                                          _darr(eta_switch, self.n)))
+
+    def diagnostics(self, box, max_records=8192):
+        buf = (Diag * max_records)()
+        cnt = ctypes.c_int32()
+        self._check(self.L.mts_batch_diagnostics(self.b, int(box), buf, max_records, ctypes.byref(cnt)))
+        return [buf[i].as_dict() for i in range(cnt.value)]
+
+    def get_fields(self, box):
+        p = self.params[box]
+        out = np.empty((20, p.nz, p.ny, p.nx), dtype=np.float64)
+        self._check(self.L.mts_batch_get_fields(self.b, int(box), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def set_fields(self, box, host):
+        host = np.ascontiguousarray(host, dtype=np.float64)
+        self._check(self.L.mts_batch_set_fields(self.b, int(box), host.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def set_tile(self, ty, tz):
+        tzs = tz if hasattr(tz, "__len__") else [tz] * self.n
+        self._check(self.L.mts_batch_set_tile(self.b, int(ty), (ctypes.c_int32 * self.n)(*[int(v) for v in tzs])))
+
+    def autotune(self, steps=3):
+        ty, tz, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        self._check(self.L.mts_batch_autotune(self.b, int(steps), ctypes.byref(ty), ctypes.byref(tz),
+                                              ctypes.byref(ms)))
+        return ty.value, tz.value, ms.value
+
+    def timing_read(self):
+        st, ms = ctypes.c_int64(), ctypes.c_double()
+        self._check(self.L.mts_batch_timing_read(self.b, ctypes.byref(st), ctypes.byref(ms)))
+        return {"steps": st.value, "ms": ms.value}

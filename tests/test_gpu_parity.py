@@ -252,3 +252,86 @@ def test_small_workload_full_run(precision):
     for r, o in zip(recs, orecs):
         assert r["sum_energy"] == pytest.approx(o["sum_eps"], rel=1e-4 if precision == "fp32" else 1e-10)
         assert max(r["gauss_rel"]) < (2e-5 if precision == "fp32" else 1e-12)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_tile_shapes_bitwise_identical(precision):
+    """Every tile shape of the z-marching kernel gives the same fields bit for bit
+    (on a box with ragged tiles in every direction)."""
+    nx, ny, nz = 70, 21, 13
+    st = rounded(I.random_full(nx, ny, nz, 11, link=0.5, mom=0.5), precision)
+    ref = None
+    for ty, tz in ((8, 32), (4, 1), (12, 5), (4, 7), (8, 13)):
+        lat = lattice(nx, ny, nz, precision, eta_ref=9.0, diag_every=4)
+        lat.set_tile(ty, tz)
+        lat.set_fields(st)
+        lat.step(12, 1.0, 0.5, 1.0)
+        got = lat.get_fields()
+        recs = lat.diagnostics()
+        if ref is None:
+            ref, rrec = got, recs
+        assert np.array_equal(got, ref), (ty, tz)
+        for a, b in zip(recs, rrec):
+            assert a["sum_energy"] == pytest.approx(b["sum_energy"], rel=1e-13)
+            assert a["wind_abs"] == b["wind_abs"] and a["pq_count2"] == b["pq_count2"]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_site_kernel_agrees_with_tiled_kernel(precision):
+    nx, ny, nz = 40, 12, 9
+    st = rounded(I.random_full(nx, ny, nz, 12, link=0.5, mom=0.5), precision)
+    out = []
+    for ty in (0, 4):
+        lat = lattice(nx, ny, nz, precision, eta_ref=9.0)
+        lat.set_tile(ty, 8)
+        lat.set_fields(st)
+        lat.step(6, 1.0, 0.5, 1.0)
+        out.append(lat.get_fields())
+    assert np.abs(out[0] - out[1]).max() <= 1e3 * U[precision] * np.abs(out[0]).max()
+    with pytest.raises(P.MtsError):
+        lat.set_tile(6, 8)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_batch_boxes_match_single_contexts(precision):
+    """Uneven boxes (sizes, seeds, eras, s, a switch of s mid-run) in one batch give, box by
+    box, the same fields bit for bit as single contexts with the same tile shape, and the
+    same diagnostic records."""
+    shapes = [(24, 16, 12), (70, 9, 5), (16, 16, 16), (33, 20, 7)]
+    eras = [0.5, 2.0 / 3.0, 0.5, 2.0 / 3.0]
+    s_b, s_a, sw = [0.0, 1.0, 0.0, 1.0], [1.0, 1.0, 1.0, 0.0], [1.8, 99.0, 1.45, 1.2]
+    kw = dict(precision=precision, diag_every=3)
+    params = [P.make_params(*sh, eta_ref=5.0 + k, **kw) for k, sh in enumerate(shapes)]
+    bt = P.Batch(params)
+    ty = 4
+    bt.set_tile(ty, [32, 2, 5, 3])
+    bt.init_fields([1000 + k for k in range(4)])
+    n = 10
+    bt.step(n, [1.0] * 4, eras, s_b, s_a, sw)
+    for k, sh in enumerate(shapes):
+        lat = lattice(*sh, eta_ref=5.0 + k, **kw)
+        lat.set_tile(ty, [32, 2, 5, 3][k])
+        lat.init_fields(1000 + k)
+        # the single context switches s by calling step twice
+        nsw = next(j for j in range(n + 1) if j == n or 1.0 + j * 0.1 >= sw[k])
+        if nsw:
+            lat.step(nsw, 1.0, eras[k], s_b[k])
+        if n - nsw:
+            lat.step(n - nsw, 1.0 + nsw * 0.1, eras[k], s_a[k])
+        got = bt.get_fields(k)
+        ref = lat.get_fields()
+        ra, rb = bt.diagnostics(k), lat.diagnostics()
+        assert len(ra) == len(rb) == 4
+        if nsw in (0, n):
+            # one call with the same eta_j: bitwise
+            assert np.array_equal(got, ref), k
+            for a, b in zip(ra, rb):
+                assert a["sum_energy"] == b["sum_energy"] and a["wind_abs"] == b["wind_abs"]
+        else:
+            # the split reference starts its second call at 1.0 + nsw*0.1 rather than
+            # accumulating j*0.1 from 1.0: eta differs in the last bit
+            assert np.abs(got - ref).max() <= 1e3 * U[precision] * np.abs(ref).max(), k
+        for a, b in zip(ra, rb):
+            assert a["s"] == b["s"] and a["eta"] == pytest.approx(b["eta"], abs=1e-12)
+    t = bt.timing_read()
+    assert t["steps"] == n and t["ms"] > 0

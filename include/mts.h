@@ -113,9 +113,10 @@ size_t mts_state_bytes(const mts_params *p);
  *               context's lifetime (its contents are the lattice).
  *   stream      hipStream_t (as void*), NULL for the null stream.
  *   out         receives the context.
- * The library allocates its own device scratch (reduction partials,
- * winding and cell bytes: 4 bytes per site, diagnostic ring); ENOMEM if
- * that fails. */
+ * The library allocates its own device scratch (reduction partials; the
+ * phase of each scalar, 2 elements per site; winding and cell bytes, 4
+ * bytes per site; occupancy bits; a diagnostic ring); ENOMEM if that
+ * fails. */
 int mts_create(const mts_params *p, void *dev_state, size_t state_bytes, void *stream, mts_ctx **out);
 
 /* Release the library's scratch.  The caller's state buffer is untouched. */
@@ -145,6 +146,16 @@ int mts_init_fields(mts_ctx *ctx, uint64_t seed);
  *              vacuum scalar mass matrix); nothing is launched. */
 int mts_step(mts_ctx *ctx, int32_t n, double eta, double era_m, double s);
 
+/* Diffusive cooling of the initial conditions (Sec. III): n forward-Euler
+ * steps of size dt_cool of the gradient flow
+ *   d phi/d eta = D^-D^+ phi - lambda/2 (|phi|^2 - sigma^2) phi
+ *   d A_i/d eta = -sum_j d_j^- F_ij + 2 e^2 Im[phi* D_i^+ phi]
+ * (and the same for psi, B) at a = 1, without the kappa coupling, as the
+ * paper prints it; momenta and electric fields are left unchanged and the
+ * step counter does not advance.  The paper cools from eta = -10 to 1 with
+ * dt_cool = 1/30.  EUNSTABLE if dt_cool (12/h^2 + mu2_max) >= 2. */
+int mts_cool(mts_ctx *ctx, int32_t n, double dt_cool);
+
 /* Drain the diagnostic records produced since the last call (oldest
  * first), synchronising the stream.  Writes at most `max` records to the
  * host array `out` and their number to *count.  Records that did not fit
@@ -159,6 +170,12 @@ int mts_diagnostics(mts_ctx *ctx, mts_diag *out, int32_t max, int32_t *count);
 int mts_get_fields(mts_ctx *ctx, double *host);
 int mts_set_fields(mts_ctx *ctx, const double *host);
 
+/* The 20 components of selected sites, host double[n][20] in the plane
+ * order of the exchange format; sites[i] = x + nx (y + ny z) < nx*ny*nz
+ * (EINVAL otherwise).  Synchronous; for spot checks of boxes too large to
+ * copy out whole. */
+int mts_get_sites(mts_ctx *ctx, const uint64_t *sites, int32_t n, double *host);
+
 /* Signed plaquette windings of the current fields (Sec. III.A), host
  * int8[6][S]: sector p (W_x, W_y, W_z), then sector q; W_rho is the
  * winding through the face normal to rho at the cell's lower corner,
@@ -170,6 +187,28 @@ int mts_get_windings(mts_ctx *ctx, int8_t *host);
  * six faces of each cell; a straight string gives 2, Sec. III.B), host
  * uint8[2][S] (sector p, then q).  Synchronous. */
 int mts_get_cells(mts_ctx *ctx, uint8_t *host);
+
+/* Robust-method bound-state segments (Sec. III.B, Sec. V.B) of the last
+ * diagnostic step's cells: the cells the fast method marks (a pierced cell
+ * of one sector with a pierced cell of the other within overlap_radius,
+ * either way round) are grouped into connected regions -- cells sharing at
+ * least a corner, periodic -- on the GPU; a region of N cells is a segment
+ * of length (N - 1) dx, kept if longer than min_length (the paper: 20 at
+ * 4096^3, i.e. more than 41 cells; 3.5 at 512^3).  Fills *out; if sizes is
+ * non-null, the region sizes in decreasing order (at most cap) and their
+ * number in *n_sizes.  Synchronous; allocates 8 bytes per site of
+ * temporary device memory.  EINVAL before any diagnostic step. */
+typedef struct mts_segments_t {
+    int64_t step;            /* step of the diagnostic record whose cells were used */
+    int64_t marked_cells;    /* fast-method pq cells                                */
+    int64_t regions;         /* connected regions of them                           */
+    int64_t n_pq;            /* regions longer than min_length: N_pq                */
+    int64_t largest;         /* cells in the largest region                         */
+    double L_pq;             /* sum of (N - 1) dx over the kept regions             */
+    double l_pq;             /* mean segment length L_pq / N_pq                     */
+    double xi_pq;            /* sqrt(V / L_pq)                                      */
+} mts_segments_t;
+int mts_segments(mts_ctx *ctx, double min_length, mts_segments_t *out, int64_t *sizes, int64_t cap, int64_t *n_sizes);
 
 /* Choose the update kernel.  ty in {4, 8, 12} selects the z-marching
  * LDS-tiled kernel with tiles of 64 x ty sites and tz >= 1 planes per

@@ -82,6 +82,9 @@ def lib():
         L.orc_step.argtypes = [mp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.POINTER(Diag)]
         L.orc_step_coeffs.argtypes = [mp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, ctypes.POINTER(Diag)]
+        L.orc_segments.argtypes = [mp, ip, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64]
+        L.orc_segments.restype = ctypes.c_int64
+        L.orc_cool.argtypes = [mp, dp, ctypes.c_int, ctypes.c_double]
         L.orc_run.argtypes = [mp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                               ctypes.c_int64, ctypes.c_int, ctypes.POINTER(Diag), ctypes.c_int]
         L.orc_run.restype = ctypes.c_int
@@ -164,6 +167,11 @@ def run(m, st, n, eta0, era_m, s, j0=0, diag_every=0):
     return [recs[i].as_dict() for i in range(nd)]
 
 
+def cool(m, st, n, dt=1.0 / 30.0):
+    """n forward-Euler steps of the diffusive cooling flow (Sec. III), in place."""
+    lib().orc_cool(ctypes.byref(m), _dp(st), n, dt)
+
+
 def windings(m, st):
     """Signed plaquette windings, int32 (6, nz, ny, nx): p (W_x, W_y, W_z), q (...)."""
     W = np.zeros((6,) + m.shape, dtype=np.int32)
@@ -186,6 +194,29 @@ def overlap(m, n, radius=None):
     cp, cq = ctypes.c_int64(), ctypes.c_int64()
     lib().orc_overlap(ctypes.byref(m), _ip(n), radius, ctypes.byref(cp), ctypes.byref(cq))
     return cp.value, cq.value
+
+
+def segments(m, n, radius=None):
+    """Sizes (cells) of the connected regions of fast-method pq cells (Sec. III.B robust
+    method), sorted in decreasing order."""
+    radius = m.overlap_radius if radius is None else radius
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    cap = m.sites
+    sizes = np.zeros(cap, dtype=np.int64)
+    k = lib().orc_segments(ctypes.byref(m), _ip(n), radius, sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), cap)
+    assert k >= 0
+    return np.sort(sizes[:k])[::-1]
+
+
+def robust(m, sizes, min_length):
+    """Robust-method estimators (Sec. III.B, V.B): segments are regions with
+    (N_cells - 1) h > min_length; L_pq = sum (N_cells - 1) h, N_pq their number,
+    l_pq = L_pq / N_pq, xi_pq = sqrt(V / L_pq)."""
+    L = [(s - 1) * m.h for s in sizes if (s - 1) * m.h > min_length]
+    Lpq = float(sum(L))
+    V = m.sites * m.h ** 3
+    return {"N_pq": len(L), "L_pq": Lpq, "l_pq": Lpq / len(L) if L else float("nan"),
+            "xi_pq": math.sqrt(V / Lpq) if Lpq > 0 else float("inf")}
 
 
 def num_threads():

@@ -249,12 +249,14 @@ double orc_hamiltonian(const orc_model *m, const double *st) {
 
 /* ------------------------------------------------------------ windings */
 
-/* covariant phase of the link: chi_mu(x) = arg(conj(phi(x)) U_mu(x) phi(x+mu)) in (-pi, pi] */
+/* covariant phase of the link: chi_mu(x) = arg(conj(phi(x)) U_mu(x) phi(x+mu)) in (-pi, pi];
+ * zero when the product vanishes (the sign of a zero does not pick a branch) */
 static double link_phase(const orc_model *m, const double *st, int sec, int mu, const int c[3]) {
     const int zero[3] = {0, 0, 0};
     int64_t s0 = site(m, c, zero);
     int64_t sp = shifted(m, c, mu, 1, mu, 0);
     cplx z = conj(get_c(m, st, c_scal(sec), s0)) * link_U(m, st, sec, mu, s0) * get_c(m, st, c_scal(sec), sp);
+    if (creal(z) == 0.0 && cimag(z) == 0.0) return 0.0; /* no phase where phi vanishes */
     double a = carg(z);
     return a <= -M_PI ? M_PI : a;
 }
@@ -343,6 +345,63 @@ void orc_overlap(const orc_model *m, const int32_t *n, int radius, int64_t *coun
             }
     *count_p = cnt[0];
     *count_q = cnt[1];
+}
+
+/*
+ * Robust-method segments (Sec. III.B, Sec. V.B): the cells marked by the
+ * fast method (a pierced cell of one sector with a pierced cell of the other
+ * in its (2r+1)^3 neighbourhood, either way round) are split into connected
+ * regions -- cells sharing at least a corner (26-neighbourhood), periodic --
+ * by a breadth-first flood fill.  Writes the size of every region to sizes
+ * (capacity cap) and returns their number (or -1 if cap is too small).
+ */
+int64_t orc_segments(const orc_model *m, const int32_t *n, int radius, int64_t *sizes, int64_t cap) {
+    const int64_t S = nsites(m);
+    uint8_t *mark = (uint8_t *)calloc((size_t)S, 1);
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)S);
+    for (int z = 0; z < m->nz; z++)
+        for (int y = 0; y < m->ny; y++)
+            for (int x = 0; x < m->nx; x++) {
+                const int c[3] = {x, y, z};
+                const int zero[3] = {0, 0, 0};
+                int64_t s0 = site(m, c, zero);
+                for (int sec = 0; sec < 2 && !mark[s0]; sec++) {
+                    if (n[sec * S + s0] == 0) continue;
+                    for (int dz = -radius; dz <= radius; dz++)
+                        for (int dy = -radius; dy <= radius; dy++)
+                            for (int dx = -radius; dx <= radius; dx++) {
+                                const int d[3] = {dx, dy, dz};
+                                if (n[(1 - sec) * S + site(m, c, d)] > 0) mark[s0] = 1;
+                            }
+                }
+            }
+    int64_t ncomp = 0;
+    for (int64_t start = 0; start < S; start++) {
+        if (mark[start] != 1) continue;
+        int64_t head = 0, tail = 0, size = 0;
+        queue[tail++] = start;
+        mark[start] = 2;
+        while (head < tail) {
+            const int64_t s0 = queue[head++];
+            size++;
+            const int c[3] = {(int)(s0 % m->nx), (int)((s0 / m->nx) % m->ny), (int)(s0 / ((int64_t)m->nx * m->ny))};
+            for (int dz = -1; dz <= 1; dz++)
+                for (int dy = -1; dy <= 1; dy++)
+                    for (int dx = -1; dx <= 1; dx++) {
+                        const int d[3] = {dx, dy, dz};
+                        const int64_t nb = site(m, c, d);
+                        if (mark[nb] == 1) {
+                            mark[nb] = 2;
+                            queue[tail++] = nb;
+                        }
+                    }
+        }
+        if (ncomp < cap) sizes[ncomp] = size;
+        ncomp++;
+    }
+    free(mark);
+    free(queue);
+    return ncomp <= cap ? ncomp : -1;
 }
 
 /* -------------------------------------------------------------- initial */
@@ -541,6 +600,36 @@ void orc_step_coeffs(const orc_model *m, double *st, double eta, double a, doubl
             double *A = st + c_link(sec, i) * S;
             const double *E = st + c_elec(sec, i) * S;
             for (int64_t s0 = 0; s0 < S; s0++) A[s0] = A[s0] + k * E[s0];
+        }
+    }
+    free(F);
+}
+
+/* Diffusive cooling of the initial conditions (Sec. III): n forward-Euler
+ * steps of size dt of the first-order flow
+ *   d phi/d eta = D^-D^+ phi - lam/2 (|phi|^2 - sig^2) phi
+ *   d A_i/d eta = -sum_j d_j^- F_ij + 2 e^2 Im[phi* D_i^+ phi]
+ * for both sectors, at a = 1 and without the kappa coupling (the printed
+ * cooling equations have none).  Momenta and electric fields are not
+ * touched. */
+void orc_cool(const orc_model *m, double *st, int n, double dt) {
+    const int64_t S = nsites(m);
+    orc_model q = *m;
+    q.kappa = 0.0;
+    double *F = (double *)malloc(sizeof(double) * 10 * (size_t)S);
+    for (int it = 0; it < n; it++) {
+        orc_forces(&q, st, 1.0, F);
+        for (int sec = 0; sec < 2; sec++) {
+            for (int part = 0; part < 2; part++) {
+                double *phi = st + (c_scal(sec) + part) * S;
+                const double *f = F + (2 * sec + part) * S;
+                for (int64_t s0 = 0; s0 < S; s0++) phi[s0] += dt * f[s0];
+            }
+            for (int i = 0; i < 3; i++) {
+                double *A = st + c_link(sec, i) * S;
+                const double *f = F + (4 + 3 * sec + i) * S;
+                for (int64_t s0 = 0; s0 < S; s0++) A[s0] += dt * f[s0];
+            }
         }
     }
     free(F);

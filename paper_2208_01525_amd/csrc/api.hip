@@ -40,12 +40,15 @@ struct mts_ctx {
     uint32_t maxblk = 0;
     uint32_t *nblk_dev = nullptr;
     TileShape tile{8, 32};       // ty = 0: per-site kernel
+    void *alpha = nullptr;       // arg(phi) per sector: T[2][plane]
     uint8_t *wabs = nullptr;     // packed |W| per sector: [2][plane]
     uint8_t *cells = nullptr;    // cell values per sector: [2][plane]
+    uint64_t *bits = nullptr;    // occupancy words per sector: [2][overlap_words] (nx % 64 == 0)
     double *ring = nullptr;      // [RING_CAP][NSLOT]
     std::vector<Meta> meta;      // one per record produced since the last drain
     int64_t produced = 0, drained = 0;
     bool have_cells = false;
+    int64_t cells_step = -1;     // step whose cells the cell arrays hold
 
     // timing
     bool timing = false;
@@ -208,7 +211,8 @@ struct TimedRegion {
 hipError_t upload_nblk(mts_ctx *c) {
     uint32_t nb[NSLOT];
     const uint32_t step_blocks = c->tile.ty == 0 ? site_blocks(c->g) : tile_blocks(c->g, c->tile);
-    for (int q = 0; q < NSLOT; q++) nb[q] = q <= SL_GV ? step_blocks : (q <= SL_OV_Q ? site_blocks(c->g) : 0);
+    for (int q = 0; q < NSLOT; q++)
+        nb[q] = q <= SL_GV ? step_blocks : (q <= SL_WIND_Q ? wind_blocks(c->g) : (q <= SL_OV_Q ? overlap_blocks(c->g) : 0));
     return hipMemcpy(c->nblk_dev, nb, sizeof(nb), hipMemcpyHostToDevice);
 }
 
@@ -222,16 +226,21 @@ hipError_t enqueue_diag_post(mts_ctx *c, const Book &b, double eta_j, double s, 
     double gcoef[2];
     const double e2[2] = {p.e_p * p.e_p, p.e_q * p.e_q};
     for (int q = 0; q < 2; q++) gcoef[q] = 2.0 * e2[q] * b.An * (1.0 + b.delta) / (1.0 + b.omega);
-    hipError_t e = launch_wind_gauss<T>(c->g, fields_of<T>(c, c->cur), moms_of<T>(c), (T)p.dx, gcoef, c->wabs,
-                                        (uint32_t)c->plane, nullptr, part, st);
-    if (e == hipSuccess) e = launch_cells(c->g, c->wabs, c->cells, (uint32_t)c->plane, st);
-    if (e == hipSuccess) e = launch_overlap(c->g, c->cells, (uint32_t)c->plane, p.overlap_radius, part, st);
+    T *alpha = static_cast<T *>(c->alpha);
+    hipError_t e = launch_phase<T>(c->g, fields_of<T>(c, c->cur), alpha, (uint32_t)c->plane, st);
+    if (e == hipSuccess)
+        e = launch_wind_gauss<T>(c->g, fields_of<T>(c, c->cur), moms_of<T>(c), alpha, (T)p.dx, gcoef, c->wabs,
+                                 (uint32_t)c->plane, nullptr, part, st);
+    if (e == hipSuccess) e = launch_cells(c->g, c->wabs, c->cells, c->bits, (uint32_t)c->plane, st);
+    if (e == hipSuccess)
+        e = launch_overlap(c->g, c->cells, c->bits, (uint32_t)c->plane, p.overlap_radius, part, st);
     double *rec = c->ring + (size_t)(c->produced % RING_CAP) * NSLOT;
     if (e == hipSuccess) e = launch_reduce(part, c->nblk_dev, rec, st);
     if (e != hipSuccess) return e;
     c->meta.push_back({c->step_count, eta_j, b.a, s});
     c->produced++;
     c->have_cells = true;
+    c->cells_step = c->step_count;
     return hipSuccess;
 }
 
@@ -387,8 +396,11 @@ int get_windings_t(mts_ctx *c, int8_t *host) {
     HIPCHK(c, hipMalloc(&tmp, bytes));
     Partials part{c->partials, c->maxblk};
     double g0[2] = {0, 0};
-    hipError_t e = launch_wind_gauss<T>(c->g, fields_of<T>(c, c->cur), moms_of<T>(c), (T)c->p.dx, g0, nullptr,
-                                        (uint32_t)c->plane, tmp, part, c->stream);
+    T *alpha = static_cast<T *>(c->alpha);
+    hipError_t e = launch_phase<T>(c->g, fields_of<T>(c, c->cur), alpha, (uint32_t)c->plane, c->stream);
+    if (e == hipSuccess)
+        e = launch_wind_gauss<T>(c->g, fields_of<T>(c, c->cur), moms_of<T>(c), alpha, (T)c->p.dx, g0, nullptr,
+                                 (uint32_t)c->plane, tmp, part, c->stream);
     std::vector<int8_t> buf(bytes);
     if (e == hipSuccess) e = hipMemcpyAsync(buf.data(), tmp, bytes, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -437,10 +449,14 @@ int mts_create(const mts_params *p, void *dev_state, size_t state_bytes, void *s
     c->tile = p->precision == MTS_FP64 ? TileShape{4, 32} : TileShape{8, 32};
     c->maxblk = site_blocks(c->g);
     for (int ty : {4, 8, 12}) c->maxblk = std::max(c->maxblk, tile_blocks(c->g, TileShape{ty, 1}));
+    c->maxblk = std::max(c->maxblk, std::max(wind_blocks(c->g), overlap_blocks(c->g)));
     hipError_t e = hipMalloc(&c->partials, sizeof(double) * NSLOT * (size_t)c->maxblk);
     if (e == hipSuccess) e = hipMalloc(&c->nblk_dev, sizeof(uint32_t) * NSLOT);
     if (e == hipSuccess) e = hipMalloc(&c->wabs, 2 * c->plane);
     if (e == hipSuccess) e = hipMalloc(&c->cells, 2 * c->plane);
+    if (e == hipSuccess) e = hipMalloc(&c->alpha, 2 * c->plane * c->esz);
+    if (e == hipSuccess && overlap_uses_bits(c->g))
+        e = hipMalloc(&c->bits, sizeof(uint64_t) * 2 * (size_t)overlap_words(c->g));
     if (e == hipSuccess) e = hipMalloc(&c->ring, sizeof(double) * NSLOT * RING_CAP);
     if (e == hipSuccess) e = upload_nblk(c);
     if (e != hipSuccess) {
@@ -459,6 +475,8 @@ int mts_destroy(mts_ctx *c) {
     (void)hipFree(c->nblk_dev);
     (void)hipFree(c->wabs);
     (void)hipFree(c->cells);
+    (void)hipFree(c->alpha);
+    (void)hipFree(c->bits);
     (void)hipFree(c->ring);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
@@ -488,6 +506,34 @@ int mts_step(mts_ctx *c, int32_t n, double eta, double era_m, double s) {
     const int rc = check_step(c, n, eta, era_m, s, s, INFINITY);
     if (rc != MTS_OK || n == 0) return rc;
     return c->p.precision == MTS_FP64 ? do_step<double>(c, n, eta, era_m, s) : do_step<float>(c, n, eta, era_m, s);
+}
+
+int mts_cool(mts_ctx *c, int32_t n, double dt_cool) {
+    if (!c) return MTS_EINVAL;
+    if (n < 0 || !(dt_cool > 0) || !std::isfinite(dt_cool)) return fail(c, MTS_EINVAL, "n >= 0 and dt_cool > 0 needed");
+    // forward Euler on the flow is stable while dt (12/h^2 + mu2_max) < 2
+    const double h = c->p.dx, bound = dt_cool * (12.0 / (h * h) + mu2_max(c->p));
+    if (!(bound < 2.0)) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "unstable: dt_cool (12/h^2 + mu2_max) = %.4g >= 2", bound);
+        return fail(c, MTS_EUNSTABLE, buf);
+    }
+    mts_params q = c->p;
+    q.kappa = 0.0;             // the printed cooling equations have no coupling term
+    q.dt = dt_cool;
+    const Book b{1.0, 0.0, 0.0, 1.0};
+    for (int32_t j = 0; j < n; j++) {
+        hipError_t e;
+        if (c->p.precision == MTS_FP64)
+            e = launch_cool<double>(c->g, fields_of<double>(c, c->cur), fields_of<double>(c, 1 - c->cur),
+                                    moms_of<double>(c), coefficients<double>(q, b, 1.0), c->stream);
+        else
+            e = launch_cool<float>(c->g, fields_of<float>(c, c->cur), fields_of<float>(c, 1 - c->cur),
+                                   moms_of<float>(c), coefficients<float>(q, b, 1.0), c->stream);
+        if (e != hipSuccess) return hipfail(c, e, "cooling kernel launch");
+        c->cur = 1 - c->cur;
+    }
+    return MTS_OK;
 }
 
 int mts_diagnostics(mts_ctx *c, mts_diag *out, int32_t max, int32_t *count) {
@@ -553,6 +599,28 @@ int mts_get_windings(mts_ctx *c, int8_t *host) {
     return c->p.precision == MTS_FP64 ? get_windings_t<double>(c, host) : get_windings_t<float>(c, host);
 }
 
+int mts_get_sites(mts_ctx *c, const uint64_t *sites, int32_t n, double *host) {
+    if (!c || n < 0 || (n > 0 && (!sites || !host))) return MTS_EINVAL;
+    if (n == 0) return MTS_OK;
+    for (int32_t i = 0; i < n; i++)
+        if (sites[i] >= c->S) return fail(c, MTS_EINVAL, "site index out of range");
+    uint64_t *dsites = nullptr;
+    double *dout = nullptr;
+    hipError_t e = hipMalloc(&dsites, sizeof(uint64_t) * n);
+    if (e == hipSuccess) e = hipMalloc(&dout, sizeof(double) * 20 * n);
+    if (e == hipSuccess) e = hipMemcpyAsync(dsites, sites, sizeof(uint64_t) * n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = c->p.precision == MTS_FP64
+                ? launch_gather<double>(fields_of<double>(c, c->cur), moms_of<double>(c), dsites, n, dout, c->stream)
+                : launch_gather<float>(fields_of<float>(c, c->cur), moms_of<float>(c), dsites, n, dout, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, dout, sizeof(double) * 20 * n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(dsites);
+    (void)hipFree(dout);
+    if (e != hipSuccess) return hipfail(c, e, "get_sites");
+    return MTS_OK;
+}
+
 int mts_get_cells(mts_ctx *c, uint8_t *host) {
     if (!c || !host) return MTS_EINVAL;
     if (!c->have_cells) return fail(c, MTS_EINVAL, "no diagnostic step has run yet");
@@ -560,6 +628,56 @@ int mts_get_cells(mts_ctx *c, uint8_t *host) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(buf.data(), c->cells, 2 * c->plane, hipMemcpyDeviceToHost));
     for (int q = 0; q < 2; q++) std::memcpy(host + (size_t)q * c->S, buf.data() + (size_t)q * c->plane, c->S);
+    return MTS_OK;
+}
+
+int mts_segments(mts_ctx *c, double min_length, mts_segments_t *out, int64_t *sizes, int64_t cap, int64_t *n_sizes) {
+    if (!c || !out || (cap > 0 && !sizes) || cap < 0) return MTS_EINVAL;
+    if (!c->have_cells) return fail(c, MTS_EINVAL, "no diagnostic step has run yet");
+    const uint32_t S = (uint32_t)c->S;
+    const uint32_t dcap = (uint32_t)std::min<uint64_t>(c->S, 1u << 24);
+    uint32_t *parent = nullptr, *count = nullptr, *dsz = nullptr, *dn = nullptr;
+    hipError_t e = hipMalloc(&parent, sizeof(uint32_t) * S);
+    if (e == hipSuccess) e = hipMalloc(&count, sizeof(uint32_t) * S);
+    if (e == hipSuccess) e = hipMalloc(&dsz, sizeof(uint32_t) * dcap);
+    if (e == hipSuccess) e = hipMalloc(&dn, sizeof(uint32_t));
+    uint32_t nreg = 0;
+    std::vector<uint32_t> hs;
+    if (e == hipSuccess)
+        e = launch_segments(c->g, c->cells, (uint32_t)c->plane, c->p.overlap_radius, parent, count, dsz, dn, dcap,
+                            c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&nreg, dn, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess && nreg <= dcap) {
+        hs.resize(nreg);
+        if (nreg) e = hipMemcpy(hs.data(), dsz, sizeof(uint32_t) * nreg, hipMemcpyDeviceToHost);
+    }
+    (void)hipFree(parent);
+    (void)hipFree(count);
+    (void)hipFree(dsz);
+    (void)hipFree(dn);
+    if (e != hipSuccess) return hipfail(c, e, "segments");
+    if (nreg > dcap) return fail(c, MTS_ENOMEM, "more regions than the size list holds");
+    std::sort(hs.begin(), hs.end(), [](uint32_t a, uint32_t b) { return a > b; });
+    const double h = c->p.dx, V = (double)c->S * h * h * h;
+    mts_segments_t r;
+    std::memset(&r, 0, sizeof r);
+    r.step = c->cells_step;
+    r.regions = (int64_t)hs.size();
+    for (uint32_t v : hs) {
+        r.marked_cells += v;
+        const double L = (double)(v - 1) * h;
+        if (L > min_length) {
+            r.n_pq++;
+            r.L_pq += L;
+        }
+    }
+    r.largest = hs.empty() ? 0 : hs[0];
+    r.l_pq = r.n_pq ? r.L_pq / (double)r.n_pq : NAN;
+    r.xi_pq = r.L_pq > 0 ? std::sqrt(V / r.L_pq) : INFINITY;
+    *out = r;
+    if (n_sizes) *n_sizes = (int64_t)hs.size();
+    for (int64_t i = 0; i < std::min<int64_t>(cap, (int64_t)hs.size()); i++) sizes[i] = hs[i];
     return MTS_OK;
 }
 

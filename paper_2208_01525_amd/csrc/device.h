@@ -48,6 +48,20 @@ struct Pi<double> {
     static constexpr double v = 3.14159265358979323846;
 };
 
+// Streaming (non-temporal) stores for data written once per step and not
+// re-read by this launch: they bypass L2 allocation, leaving L2 to the
+// halo rows that neighbouring tiles share.
+template <typename T>
+__device__ __forceinline__ void st_stream(T *p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(cx<T> *p, cx<T> v) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    v2 w = {v.re, v.im};
+    __builtin_nontemporal_store(w, reinterpret_cast<v2 *>(p));
+}
+
 // link phasor exp(-i h A)
 template <typename T>
 __device__ __forceinline__ cx<T> phasor(T hA) {

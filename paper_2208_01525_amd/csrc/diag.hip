@@ -1,0 +1,356 @@
+// diag.hip -- post-step diagnostic kernels of the U(1)xU(1) lattice update
+// (Correia & Martins, arXiv:2208.01525, Sec. III.A-B and the Gauss law of
+// Sec. II): plaquette windings, the Gauss residual, cell values, the
+// fast-method bound-state overlap, and the final fixed-order reduction.
+//
+// Windings.  With alpha(x) = arg phi(x), the covariant link phase is
+//   chi_mu(x) = arg(conj(phi(x)) U_mu(x) phi(x+mu)) = wrap(alpha(x+mu) - alpha(x) - h A_mu(x)),
+// wrap into (-pi, pi], so one atan2 per site replaces a sincos and an atan2
+// per link.  A link whose chi lies within `guard` of the branch cut (or has
+// an endpoint with phi = 0, or |h A| too large for the precision) is
+// recomputed in FP64 from the complex product, so the windings equal an FP64
+// evaluation of the same inputs bit for bit.  The winding through the face
+// normal to rho, (mu, nu, rho) cyclic, is
+//   W_rho(x) = rint([chi_mu(x) + chi_nu(x+mu) - chi_mu(x+nu) - chi_nu(x) + theta_mu,nu(x)] / 2 pi).
+//
+// Overlap.  When nx is a multiple of 64, the cell kernel also packs "cell
+// pierced" into 64-bit words along x with a wave ballot; a cell of one sector
+// counts when the 3x3x3 dilation of the other sector's mask covers it, which
+// is shifts and ORs of 27 words and a popcount per 64 cells.  Other boxes use
+// a direct scan of the 27 neighbouring cell bytes.
+#include "device.h"
+#include "kernels.h"
+
+namespace mts {
+
+namespace {
+
+constexpr int DX = 64, DY = 4, DZ = 4;   // wind/Gauss blocks: 64 x 4 columns, DZ planes per thread
+
+template <typename T>
+struct Guard;
+template <>
+struct Guard<float> {
+    static constexpr float cut = 1e-4f, big = 1e3f;
+};
+template <>
+struct Guard<double> {
+    static constexpr double cut = 1e-9, big = 1e6;
+};
+
+template <typename T>
+__device__ __forceinline__ T wrap_pi(T v) {   // into [-pi, pi], +pi for the cut itself
+    const T two_pi = T(2) * Pi<T>::v;
+    T r = v - two_pi * rint_t(v * (T(0.5) / Pi<T>::v));
+    return r <= -Pi<T>::v ? Pi<T>::v : r;
+}
+
+// FP64 link phase from the complex product, -pi mapped to +pi.
+__device__ __noinline__ double exact_link_phase(double are, double aim, double bre, double bim, double hA) {
+    double s, c;
+    sincos(hA, &s, &c);
+    const double ure = c, uim = -s;
+    // (conj(a) * U) * b
+    const double tre = are * ure + aim * uim, tim = are * uim - aim * ure;
+    const double zre = tre * bre - tim * bim, zim = tre * bim + tim * bre;
+    double ang = atan2(zim, zre);
+    return ang <= -Pi<double>::v ? Pi<double>::v : ang;
+}
+
+// chi of the link from site a to site b (phases aa, ab; link hA), guarded.
+template <typename T>
+__device__ __forceinline__ T link_chi(T aa, T ab, T hA, const cx<T> *phi, uint32_t sa, uint32_t sb) {
+    T chi = wrap_pi((ab - aa) - hA);
+    const bool zero = isnan(aa) || isnan(ab);
+    if (zero || fabs(chi) > Pi<T>::v - Guard<T>::cut || fabs(hA) > Guard<T>::big) {
+        const cx<T> a = phi[sa], b = phi[sb];
+        const bool z0 = (a.re == T(0) && a.im == T(0)) || (b.re == T(0) && b.im == T(0));
+        chi = z0 ? T(0) : (T)exact_link_phase(a.re, a.im, b.re, b.im, (double)hA);
+    }
+    return chi;
+}
+
+__device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+}  // namespace
+
+// ---------------------------------------------------------------- phases
+
+template <typename T>
+__global__ __launch_bounds__(256) void phase_kernel(Fields<T> f, T *alpha, uint32_t plane, uint32_t S) {
+    const uint32_t s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= S) return;
+#pragma unroll
+    for (int sec = 0; sec < 2; sec++) {
+        const cx<T> p = f.phi[sec][s];
+        alpha[(size_t)sec * plane + s] = (p.re == T(0) && p.im == T(0)) ? T(NAN) : atan2_t(p.im, p.re);
+    }
+}
+
+template <typename T>
+hipError_t launch_phase(const Geom &g, Fields<T> f, T *alpha, uint32_t plane, hipStream_t st) {
+    const uint32_t S = g.nxy * (uint32_t)g.nz;
+    phase_kernel<T><<<(S + 255) / 256, 256, 0, st>>>(f, alpha, plane, S);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- windings and Gauss
+
+uint32_t wind_blocks(const Geom &g) {
+    return (uint32_t)((g.nx + DX - 1) / DX) * (uint32_t)((g.ny + DY - 1) / DY) * (uint32_t)((g.nz + DZ - 1) / DZ);
+}
+
+template <typename T>
+__global__ __launch_bounds__(DX *DY) void wind_gauss_kernel(Geom g, Fields<T> f, Moms<T> mom, const T *alpha, T h,
+                                                            double g_p, double g_q, uint8_t *wabs, uint32_t plane,
+                                                            int8_t *signed_out, Partials part) {
+    const int x = blockIdx.x * DX + threadIdx.x;
+    const int y = blockIdx.y * DY + threadIdx.y;
+    double acc[6] = {0, 0, 0, 0, 0, 0};   // gauss_abs p,q; gauss_scale p,q; wind p,q
+    if (x < g.nx && y < g.ny) {
+        const int xp = wrap1(x + 1, g.nx), xm = wrap1(x - 1, g.nx);
+        const int yp = wrap1(y + 1, g.ny), ym = wrap1(y - 1, g.ny);
+        const T inv2pi = T(0.5) / Pi<T>::v;
+        const int z1 = min((int)(blockIdx.z + 1) * DZ, g.nz);
+        for (int z = blockIdx.z * DZ; z < z1; z++) {
+            const int zp = wrap1(z + 1, g.nz), zm = wrap1(z - 1, g.nz);
+            const uint32_t nx = g.nx, nxy = g.nxy;
+            const uint32_t s = x + nx * y + nxy * z;
+            const uint32_t s_x = xp + nx * y + nxy * z, s_y = x + nx * yp + nxy * z, s_z = x + nx * y + nxy * zp;
+            const uint32_t s_xy = xp + nx * yp + nxy * z, s_xz = xp + nx * y + nxy * zp, s_yz = x + nx * yp + nxy * zp;
+#pragma unroll
+            for (int sec = 0; sec < 2; sec++) {
+                const T *al = alpha + (size_t)sec * plane;
+                const cx<T> *P = f.phi[sec];
+                const T *Ax = f.A[sec][0], *Ay = f.A[sec][1], *Az = f.A[sec][2];
+                const T a0 = al[s], ax = al[s_x], ay = al[s_y], az = al[s_z];
+                const T axy = al[s_xy], axz = al[s_xz], ayz = al[s_yz];
+                const T hx = h * Ax[s], hy = h * Ay[s], hz = h * Az[s];
+                const T hy_px = h * Ay[s_x], hz_px = h * Az[s_x];
+                const T hx_py = h * Ax[s_y], hz_py = h * Az[s_y];
+                const T hx_pz = h * Ax[s_z], hy_pz = h * Ay[s_z];
+                const T chx = link_chi(a0, ax, hx, P, s, s_x);
+                const T chy = link_chi(a0, ay, hy, P, s, s_y);
+                const T chz = link_chi(a0, az, hz, P, s, s_z);
+                const T chy_px = link_chi(ax, axy, hy_px, P, s_x, s_xy);
+                const T chz_px = link_chi(ax, axz, hz_px, P, s_x, s_xz);
+                const T chx_py = link_chi(ay, axy, hx_py, P, s_y, s_xy);
+                const T chz_py = link_chi(ay, ayz, hz_py, P, s_y, s_yz);
+                const T chx_pz = link_chi(az, axz, hx_pz, P, s_z, s_xz);
+                const T chy_pz = link_chi(az, ayz, hy_pz, P, s_z, s_yz);
+                // unwrapped plaquette angles h [A_mu(x) + A_nu(x+mu) - A_mu(x+nu) - A_nu(x)]
+                const T txy = plaq(h, Ax[s], Ay[s_x], Ax[s_y], Ay[s]);
+                const T tyz = plaq(h, Ay[s], Az[s_y], Ay[s_z], Az[s]);
+                const T tzx = plaq(h, Az[s], Ax[s_z], Az[s_x], Ax[s]);
+                const int Wz = (int)rint_t(((((chx + chy_px) - chx_py) - chy) + txy) * inv2pi);
+                const int Wx = (int)rint_t(((((chy + chz_py) - chy_pz) - chz) + tyz) * inv2pi);
+                const int Wy = (int)rint_t(((((chz + chx_pz) - chz_px) - chx) + tzx) * inv2pi);
+                if (signed_out) {
+                    auto cl = [](int w) { return (int8_t)(w > 127 ? 127 : (w < -127 ? -127 : w)); };
+                    signed_out[(size_t)(3 * sec + 0) * plane + s] = cl(Wx);
+                    signed_out[(size_t)(3 * sec + 1) * plane + s] = cl(Wy);
+                    signed_out[(size_t)(3 * sec + 2) * plane + s] = cl(Wz);
+                    continue;
+                }
+                const int aWx = abs(Wx), aWy = abs(Wy), aWz = abs(Wz);
+                wabs[(size_t)sec * plane + s] = (uint8_t)(min(aWx, 3) | (min(aWy, 3) << 2) | (min(aWz, 3) << 4));
+                acc[4 + sec] += (double)(aWx + aWy + aWz);
+
+                // Gauss residual at n+1/2: div E^{n+1/2} - g Im[conj(phi^n) Pi^{n+1/2}]
+                const T *Ex = mom.E[sec][0], *Ey = mom.E[sec][1], *Ez = mom.E[sec][2];
+                const uint32_t s_mx = xm + nx * y + nxy * z, s_my = x + nx * ym + nxy * z, s_mz = x + nx * y + nxy * zm;
+                const T div = (((Ex[s] - Ex[s_mx]) + (Ey[s] - Ey[s_my])) + (Ez[s] - Ez[s_mz])) / h;
+                const T gs = (T)(sec == 0 ? g_p : g_q);
+                const T grho = gs * imc(P[s], mom.pi[sec][s]);
+                acc[sec] += (double)fabs(div - grho);
+                acc[2 + sec] += (double)fabs(div) + (double)fabs(grho);
+            }
+        }
+    }
+    if (!signed_out) {
+        const uint32_t blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+        block_sum_store<6, (DX * DY) / 64>(acc, part, SL_GAUSS_ABS_P, blk);
+    }
+}
+
+template <typename T>
+hipError_t launch_wind_gauss(const Geom &g, Fields<T> f, Moms<T> mom, const T *alpha, T h, const double gcoef[2],
+                             uint8_t *wabs, uint32_t plane, int8_t *signed_out, Partials part, hipStream_t st) {
+    dim3 block(DX, DY, 1);
+    dim3 grid((g.nx + DX - 1) / DX, (g.ny + DY - 1) / DY, (g.nz + DZ - 1) / DZ);
+    wind_gauss_kernel<T><<<grid, block, 0, st>>>(g, f, mom, alpha, h, gcoef[0], gcoef[1], wabs, plane, signed_out,
+                                                 part);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- cells
+
+bool overlap_uses_bits(const Geom &g) { return g.nx % 64 == 0; }
+
+uint32_t overlap_words(const Geom &g) { return (uint32_t)(g.nx / 64) * (uint32_t)g.ny * (uint32_t)g.nz; }
+
+// Cell value = sum of |W| over the six faces of the cell [x, x+1]^3; with
+// `bits`, also the 64-cell occupancy words of each sector.
+__global__ __launch_bounds__(256) void cells_kernel(Geom g, const uint8_t *wabs, uint8_t *cells, uint64_t *bits,
+                                                    uint32_t plane, uint32_t nwords) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int z = blockIdx.z;
+    const bool in = x < g.nx && y < g.ny;
+    uint32_t n[2] = {0, 0};
+    if (in) {
+        const uint32_t s = x + g.nx * y + g.nxy * z;
+        const uint32_t sx = wrap1(x + 1, g.nx) + g.nx * y + g.nxy * z;
+        const uint32_t sy = x + g.nx * wrap1(y + 1, g.ny) + g.nxy * z;
+        const uint32_t sz = x + g.nx * y + g.nxy * wrap1(z + 1, g.nz);
+#pragma unroll
+        for (int sec = 0; sec < 2; sec++) {
+            const uint8_t *w = wabs + (size_t)sec * plane;
+            const uint32_t w0 = w[s];
+            n[sec] = (w0 & 3) + (w[sx] & 3) + ((w0 >> 2) & 3) + ((w[sy] >> 2) & 3) + ((w0 >> 4) & 3) + ((w[sz] >> 4) & 3);
+            cells[(size_t)sec * plane + s] = (uint8_t)n[sec];
+        }
+    }
+    if (bits) {   // nx % 64 == 0: the wave is one 64-cell word of one row
+        const uint64_t mp = __ballot(in && n[0] > 0), mq = __ballot(in && n[1] > 0);
+        if (threadIdx.x == 0 && in) {
+            const uint32_t wi = (uint32_t)(x / 64) + (uint32_t)(g.nx / 64) * ((uint32_t)y + (uint32_t)g.ny * z);
+            bits[wi] = mp;
+            bits[(size_t)nwords + wi] = mq;
+        }
+    }
+}
+
+hipError_t launch_cells(const Geom &g, const uint8_t *wabs, uint8_t *cells, uint64_t *bits, uint32_t plane,
+                        hipStream_t st) {
+    dim3 block(64, 4, 1);
+    dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+    cells_kernel<<<grid, block, 0, st>>>(g, wabs, cells, overlap_uses_bits(g) ? bits : nullptr, plane,
+                                         overlap_words(g));
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- overlap
+
+uint32_t overlap_blocks(const Geom &g) {
+    if (overlap_uses_bits(g)) return (overlap_words(g) + 255) / 256;
+    return (uint32_t)((g.nx + 63) / 64) * (uint32_t)((g.ny + 3) / 4) * (uint32_t)g.nz;
+}
+
+// x-dilation of the word at (xw, y, z) by one cell with periodic wrap
+__device__ __forceinline__ uint64_t dilate_x(const uint64_t *m, uint32_t row, int xw, int nw) {
+    const uint64_t w = m[row + xw];
+    const uint64_t l = m[row + (xw == 0 ? nw - 1 : xw - 1)], r = m[row + (xw + 1 == nw ? 0 : xw + 1)];
+    return w | (w << 1) | (w >> 1) | (l >> 63) | (r << 63);
+}
+
+__global__ __launch_bounds__(256) void overlap_bits_kernel(Geom g, const uint64_t *bits, uint32_t nwords, int radius,
+                                                           Partials part) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    double acc[2] = {0, 0};
+    if (i < nwords) {
+        const int nw = g.nx / 64;
+        const int xw = i % nw, y = (i / nw) % g.ny, z = i / (nw * g.ny);
+#pragma unroll
+        for (int sec = 0; sec < 2; sec++) {
+            const uint64_t *own = bits + (size_t)sec * nwords, *oth = bits + (size_t)(1 - sec) * nwords;
+            uint64_t d = 0;
+            if (radius == 0) {
+                d = oth[i];
+            } else {
+                for (int dz = -1; dz <= 1; dz++)
+                    for (int dy = -1; dy <= 1; dy++) {
+                        const uint32_t row =
+                            (uint32_t)nw * ((uint32_t)wrap1(y + dy, g.ny) + (uint32_t)g.ny * (uint32_t)wrap1(z + dz, g.nz));
+                        d |= dilate_x(oth, row, xw, nw);
+                    }
+            }
+            acc[sec] = (double)__popcll(own[i] & d);
+        }
+    }
+    block_sum_store<2, 4>(acc, part, SL_OV_P, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void overlap_bytes_kernel(Geom g, const uint8_t *cells, uint32_t plane, int radius,
+                                                            Partials part) {
+    const int x = blockIdx.x * 64 + threadIdx.x;
+    const int y = blockIdx.y * 4 + threadIdx.y;
+    const int z = blockIdx.z;
+    double acc[2] = {0, 0};
+    if (x < g.nx && y < g.ny) {
+        const uint32_t s = x + g.nx * y + g.nxy * z;
+#pragma unroll
+        for (int sec = 0; sec < 2; sec++) {
+            if (cells[(size_t)sec * plane + s] == 0) continue;
+            const uint8_t *o = cells + (size_t)(1 - sec) * plane;
+            bool hit = false;
+            for (int dz = -radius; dz <= radius && !hit; dz++) {
+                const int zz = wrap1(z + dz, g.nz);
+                for (int dy = -radius; dy <= radius && !hit; dy++) {
+                    const int yy = wrap1(y + dy, g.ny);
+                    for (int dx = -radius; dx <= radius && !hit; dx++) {
+                        const int xx = wrap1(x + dx, g.nx);
+                        hit = o[xx + g.nx * yy + g.nxy * zz] != 0;
+                    }
+                }
+            }
+            acc[sec] = hit ? 1.0 : 0.0;
+        }
+    }
+    const uint32_t blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    block_sum_store<2, 4>(acc, part, SL_OV_P, blk);
+}
+
+hipError_t launch_overlap(const Geom &g, const uint8_t *cells, const uint64_t *bits, uint32_t plane, int radius,
+                          Partials part, hipStream_t st) {
+    if (overlap_uses_bits(g)) {
+        const uint32_t nw = overlap_words(g);
+        overlap_bits_kernel<<<(nw + 255) / 256, 256, 0, st>>>(g, bits, nw, radius, part);
+    } else {
+        dim3 block(64, 4, 1);
+        dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+        overlap_bytes_kernel<<<grid, block, 0, st>>>(g, cells, plane, radius, part);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- final reduce
+
+// One block per slot; thread t sums partials t, t + 1024, ... in order (four
+// independent running sums combined in a fixed order), then a fixed tree.
+__global__ __launch_bounds__(1024) void reduce_kernel(Partials part, const uint32_t *nblk, double *rec) {
+    __shared__ double red[1024];
+    const int slot = blockIdx.x;
+    const uint32_t n = nblk[slot];
+    const double *p = part.base + (size_t)slot * part.maxblk;
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    uint32_t i = threadIdx.x;
+    for (; i + 3 * 1024 < n; i += 4 * 1024) {
+        t0 += p[i];
+        t1 += p[i + 1024];
+        t2 += p[i + 2 * 1024];
+        t3 += p[i + 3 * 1024];
+    }
+    for (; i < n; i += 1024) t0 += p[i];
+    red[threadIdx.x] = (t0 + t1) + (t2 + t3);
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) rec[slot] = red[0];
+}
+
+hipError_t launch_reduce(Partials part, const uint32_t *nblk_per_slot_dev, double *rec, hipStream_t st) {
+    reduce_kernel<<<NSLOT, 1024, 0, st>>>(part, nblk_per_slot_dev, rec);
+    return hipGetLastError();
+}
+
+template hipError_t launch_phase<float>(const Geom &, Fields<float>, float *, uint32_t, hipStream_t);
+template hipError_t launch_phase<double>(const Geom &, Fields<double>, double *, uint32_t, hipStream_t);
+template hipError_t launch_wind_gauss<float>(const Geom &, Fields<float>, Moms<float>, const float *, float,
+                                             const double[2], uint8_t *, uint32_t, int8_t *, Partials, hipStream_t);
+template hipError_t launch_wind_gauss<double>(const Geom &, Fields<double>, Moms<double>, const double *, double,
+                                              const double[2], uint8_t *, uint32_t, int8_t *, Partials, hipStream_t);
+
+}  // namespace mts

@@ -77,6 +77,11 @@ template <typename T>
 hipError_t launch_step(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, const StepCoef<T> &c,
                        bool diag, Partials part, hipStream_t st);
 
+// One forward-Euler step of the diffusive cooling flow: out = in + k force,
+// momenta untouched (c built with kappa = 0, a = 1, k = the cooling step).
+template <typename T>
+hipError_t launch_cool(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, const StepCoef<T> &c, hipStream_t st);
+
 // The same step with the z-marching LDS-tiled kernel: a workgroup owns a
 // 64 x ty column of sites over tz planes; ty in {4, 8, 12}.
 struct TileShape {
@@ -102,18 +107,36 @@ template <typename T>
 hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32_t nblk, int parity,
                                   const StepCoef<T> *coef_dev, bool diag, int ty, hipStream_t st);
 
+// Phase alpha = arg(phi) of every site and sector into alpha[2][plane]
+// (NaN where phi = 0), input of the winding kernel.
+template <typename T>
+hipError_t launch_phase(const Geom &g, Fields<T> f, T *alpha, uint32_t plane, hipStream_t st);
+
 // Windings of `f` (packed |W| per sector into wabs[2][plane] bytes, sum |W|
 // into partials) and the Gauss residual of (f, mom) with g_sigma.
 // If `signed_out` is non-null the signed windings go there as int8[6][plane]
 // and nothing else is written.
 template <typename T>
-hipError_t launch_wind_gauss(const Geom &g, Fields<T> f, Moms<T> mom, T h, const double gcoef[2],
+hipError_t launch_wind_gauss(const Geom &g, Fields<T> f, Moms<T> mom, const T *alpha, T h, const double gcoef[2],
                              uint8_t *wabs, uint32_t plane, int8_t *signed_out, Partials part, hipStream_t st);
+uint32_t wind_blocks(const Geom &g);
 
-// Cell values from packed |W| (cells[2][plane] bytes), then the overlap counts.
-hipError_t launch_cells(const Geom &g, const uint8_t *wabs, uint8_t *cells, uint32_t plane, hipStream_t st);
-hipError_t launch_overlap(const Geom &g, const uint8_t *cells, uint32_t plane, int radius, Partials part,
-                          hipStream_t st);
+// Cell values from packed |W| (cells[2][plane] bytes) and, when nx is a
+// multiple of 64, the 64-cell occupancy words bits[2][overlap_words]; then
+// the overlap counts.
+bool overlap_uses_bits(const Geom &g);
+uint32_t overlap_words(const Geom &g);
+uint32_t overlap_blocks(const Geom &g);
+hipError_t launch_cells(const Geom &g, const uint8_t *wabs, uint8_t *cells, uint64_t *bits, uint32_t plane,
+                        hipStream_t st);
+hipError_t launch_overlap(const Geom &g, const uint8_t *cells, const uint64_t *bits, uint32_t plane, int radius,
+                          Partials part, hipStream_t st);
+
+// Robust-method regions of the fast-method pq cells (union-find): region
+// sizes into sizes[0 .. min(*n_out, cap)), *n_out = number of regions.
+// parent and count are scratch of one uint32 per site.
+hipError_t launch_segments(const Geom &g, const uint8_t *cells, uint32_t plane, int radius, uint32_t *parent,
+                           uint32_t *count, uint32_t *sizes, uint32_t *n_out, uint32_t cap, hipStream_t st);
 
 // Fixed-order FP64 sum of every slot's partials into rec[NSLOT].
 hipError_t launch_reduce(Partials part, const uint32_t *nblk_per_slot_dev, double *rec, hipStream_t st);
@@ -122,6 +145,10 @@ hipError_t launch_reduce(Partials part, const uint32_t *nblk_per_slot_dev, doubl
 template <typename T>
 hipError_t launch_init(const Geom &g, Fields<T> f, Moms<T> mom, uint64_t seed, double sig_p, double sig_q,
                        hipStream_t st);
+
+// Gather the 20 components (host exchange order) of n sites into out[n][20].
+template <typename T>
+hipError_t launch_gather(Fields<T> f, Moms<T> mom, const uint64_t *sites, int n, double *out, hipStream_t st);
 
 // Number of blocks the per-site kernels use for geometry g (partials needed).
 uint32_t site_blocks(const Geom &g);

@@ -54,9 +54,13 @@ uint32_t site_blocks(const Geom &g) {
 
 // ------------------------------------------------------------ the update
 
-template <typename T, bool DIAG>
+// MODE 0: leapfrog step; 1: step with the integer-time sums; 2: one
+// forward-Euler step of the diffusive cooling flow (fields move along their
+// forces, momenta untouched; the host passes kappa = 0, a = 1, k = d eta).
+template <typename T, int MODE>
 __global__ __launch_bounds__(BX *BY) void step_site_kernel(Geom g, Fields<T> in, Fields<T> out, Moms<T> mom,
                                                            StepCoef<T> c, Partials part) {
+    constexpr bool DIAG = MODE == 1, COOL = MODE == 2;
     const int x = blockIdx.x * BX + threadIdx.x;
     const int y = blockIdx.y * BY + threadIdx.y;
     const int z = blockIdx.z;
@@ -97,15 +101,19 @@ __global__ __launch_bounds__(BX *BY) void step_site_kernel(Geom g, Fields<T> in,
             F.re = c.inv_h2 * lap.re - br * f.re;
             F.im = c.inv_h2 * lap.im - br * f.im;
 
-            // scalar kick (in place) and drift
-            const cx<T> p0 = mom.pi[sec][q.s];
-            cx<T> p1;
-            p1.re = c.cpi * p0.re + c.kpi * F.re;
-            p1.im = c.cpi * p0.im + c.kpi * F.im;
-            mom.pi[sec][q.s] = p1;
-            cx<T> fn;
-            fn.re = f.re + c.k * p1.re;
-            fn.im = f.im + c.k * p1.im;
+            // scalar kick (in place) and drift; cooling moves phi along F
+            cx<T> p0{T(0), T(0)}, p1{T(0), T(0)}, fn;
+            if constexpr (COOL) {
+                fn.re = f.re + c.k * F.re;
+                fn.im = f.im + c.k * F.im;
+            } else {
+                p0 = mom.pi[sec][q.s];
+                p1.re = c.cpi * p0.re + c.kpi * F.re;
+                p1.im = c.cpi * p0.im + c.kpi * F.im;
+                mom.pi[sec][q.s] = p1;
+                fn.re = f.re + c.k * p1.re;
+                fn.im = f.im + c.k * p1.im;
+            }
             out.phi[sec][q.s] = fn;
 
             // plaquettes around the three links of x
@@ -125,14 +133,23 @@ __global__ __launch_bounds__(BX *BY) void step_site_kernel(Geom g, Fields<T> in,
             const T Mz = -c.inv_h3 * ((sxz_mx - sxz) + (syz_my - syz));
             const T Jx = c.cur[sec] * imc(f, wx), Jy = c.cur[sec] * imc(f, wy), Jz = c.cur[sec] * imc(f, wz);
 
-            T *Ex = mom.E[sec][0], *Ey = mom.E[sec][1], *Ez = mom.E[sec][2];
-            const T e0x = Ex[q.s], e0y = Ey[q.s], e0z = Ez[q.s];
-            const T e1x = c.cE * e0x + c.kE * (Mx + Jx);
-            const T e1y = c.cE * e0y + c.kE * (My + Jy);
-            const T e1z = c.cE * e0z + c.kE * (Mz + Jz);
-            Ex[q.s] = e1x;
-            Ey[q.s] = e1y;
-            Ez[q.s] = e1z;
+            T e0x = 0, e0y = 0, e0z = 0, e1x, e1y, e1z;
+            if constexpr (COOL) {
+                e1x = Mx + Jx;          // the links flow along their force
+                e1y = My + Jy;
+                e1z = Mz + Jz;
+            } else {
+                T *Ex = mom.E[sec][0], *Ey = mom.E[sec][1], *Ez = mom.E[sec][2];
+                e0x = Ex[q.s];
+                e0y = Ey[q.s];
+                e0z = Ez[q.s];
+                e1x = c.cE * e0x + c.kE * (Mx + Jx);
+                e1y = c.cE * e0y + c.kE * (My + Jy);
+                e1z = c.cE * e0z + c.kE * (Mz + Jz);
+                Ex[q.s] = e1x;
+                Ey[q.s] = e1y;
+                Ez[q.s] = e1z;
+            }
             out.A[sec][0][q.s] = ax + c.k * e1x;
             out.A[sec][1][q.s] = ay + c.k * e1y;
             out.A[sec][2][q.s] = az + c.k * e1z;
@@ -184,198 +201,17 @@ hipError_t launch_step(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, 
     dim3 block(BX, BY, 1);
     dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY, g.nz);
     if (diag)
-        step_site_kernel<T, true><<<grid, block, 0, st>>>(g, in, out, mom, c, part);
+        step_site_kernel<T, 1><<<grid, block, 0, st>>>(g, in, out, mom, c, part);
     else
-        step_site_kernel<T, false><<<grid, block, 0, st>>>(g, in, out, mom, c, part);
+        step_site_kernel<T, 0><<<grid, block, 0, st>>>(g, in, out, mom, c, part);
     return hipGetLastError();
-}
-
-// ------------------------------------------------------------ windings and Gauss
-
-// chi = arg(conj(a) exp(-i h A) b) in (-pi, pi].  Near the branch cut
-// (Re z < 0, |Im z| < 1e-4 |z|) a float link is recomputed in double so that
-// the side of the cut, and hence the winding, matches an FP64 evaluation of
-// the same float inputs.
-template <typename T>
-__device__ __forceinline__ T link_phase(cx<T> a, cx<T> b, T A, T h) {
-    const cx<T> z = cmul(cmulc(a, phasor<T>(h * A)), b);
-    T ang;
-    if constexpr (sizeof(T) == 4) {
-        if (z.re < 0.0f && fabsf(z.im) < 1e-4f * (fabsf(z.re) + fabsf(z.im))) {
-            const cx<double> ad{a.re, a.im}, bd{b.re, b.im};
-            const cx<double> zd = cmul(cmulc(ad, phasor<double>((double)h * (double)A)), bd);
-            double ad_ang = atan2(zd.im, zd.re);
-            if (ad_ang <= -Pi<double>::v) ad_ang = Pi<double>::v;
-            return (float)ad_ang;
-        }
-    }
-    ang = atan2_t(z.im, z.re);
-    if (ang <= -Pi<T>::v) ang = Pi<T>::v;
-    return ang;
 }
 
 template <typename T>
-__global__ __launch_bounds__(BX *BY) void wind_gauss_kernel(Geom g, Fields<T> f, Moms<T> mom, T h, double g_p,
-                                                            double g_q, uint8_t *wabs, uint32_t plane,
-                                                            int8_t *signed_out, Partials part) {
-    const int x = blockIdx.x * BX + threadIdx.x;
-    const int y = blockIdx.y * BY + threadIdx.y;
-    const int z = blockIdx.z;
-    double acc[6] = {0, 0, 0, 0, 0, 0};   // gauss_abs p,q; gauss_scale p,q; wind p,q
-    if (x < g.nx && y < g.ny) {
-        const Site q = site_of(g, x, y, z);
-        // second neighbours for the links of the neighbouring sites
-        const int xp = x + 1 == g.nx ? 0 : x + 1, yp = y + 1 == g.ny ? 0 : y + 1, zp = z + 1 == g.nz ? 0 : z + 1;
-        const uint32_t xp_yp = xp + g.nx * yp + g.nxy * z;
-        const uint32_t xp_zp = xp + g.nx * y + g.nxy * zp;
-        const uint32_t yp_zp = x + g.nx * yp + g.nxy * zp;
-        const T two_pi_inv = T(0.5) / Pi<T>::v;
-#pragma unroll
-        for (int sec = 0; sec < 2; sec++) {
-            const cx<T> *P = f.phi[sec];
-            const T *Ax = f.A[sec][0], *Ay = f.A[sec][1], *Az = f.A[sec][2];
-            const cx<T> p0 = P[q.s], pxp = P[q.xp], pyp = P[q.yp], pzp = P[q.zp];
-            const T ax = Ax[q.s], ay = Ay[q.s], az = Az[q.s];
-            const T chx = link_phase(p0, pxp, ax, h);
-            const T chy = link_phase(p0, pyp, ay, h);
-            const T chz = link_phase(p0, pzp, az, h);
-            const T chy_px = link_phase(pxp, P[xp_yp], Ay[q.xp], h);
-            const T chz_px = link_phase(pxp, P[xp_zp], Az[q.xp], h);
-            const T chx_py = link_phase(pyp, P[xp_yp], Ax[q.yp], h);
-            const T chz_py = link_phase(pyp, P[yp_zp], Az[q.yp], h);
-            const T chx_pz = link_phase(pzp, P[xp_zp], Ax[q.zp], h);
-            const T chy_pz = link_phase(pzp, P[yp_zp], Ay[q.zp], h);
-            const T txy = plaq(h, ax, Ay[q.xp], Ax[q.yp], ay);
-            const T tyz = plaq(h, ay, Az[q.yp], Ay[q.zp], az);
-            const T tzx = plaq(h, az, Ax[q.zp], Az[q.xp], ax);
-            const int Wz = (int)rint_t(((((chx + chy_px) - chx_py) - chy) + txy) * two_pi_inv);
-            const int Wx = (int)rint_t(((((chy + chz_py) - chy_pz) - chz) + tyz) * two_pi_inv);
-            const int Wy = (int)rint_t(((((chz + chx_pz) - chz_px) - chx) + tzx) * two_pi_inv);
-            if (signed_out) {
-                auto cl = [](int w) { return (int8_t)(w > 127 ? 127 : (w < -127 ? -127 : w)); };
-                signed_out[(size_t)(3 * sec + 0) * plane + q.s] = cl(Wx);
-                signed_out[(size_t)(3 * sec + 1) * plane + q.s] = cl(Wy);
-                signed_out[(size_t)(3 * sec + 2) * plane + q.s] = cl(Wz);
-                continue;
-            }
-            const int aWx = abs(Wx), aWy = abs(Wy), aWz = abs(Wz);
-            wabs[(size_t)sec * plane + q.s] =
-                (uint8_t)(min(aWx, 3) | (min(aWy, 3) << 2) | (min(aWz, 3) << 4));
-            acc[4 + sec] = (double)(aWx + aWy + aWz);
-
-            // Gauss residual at n+1/2: div E^{n+1/2} - g Im[conj(phi^n) Pi^{n+1/2}]
-            const T *Ex = mom.E[sec][0], *Ey = mom.E[sec][1], *Ez = mom.E[sec][2];
-            const T div = (((Ex[q.s] - Ex[q.xm]) + (Ey[q.s] - Ey[q.ym])) + (Ez[q.s] - Ez[q.zm])) / h;
-            const T gs = (T)(sec == 0 ? g_p : g_q);
-            const T grho = gs * imc(p0, mom.pi[sec][q.s]);
-            const T C = div - grho;
-            acc[sec] = (double)fabs(C);
-            acc[2 + sec] = (double)fabs(div) + (double)fabs(grho);
-        }
-    }
-    if (!signed_out) {
-        const uint32_t blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-        block_sum_store<6, (BX * BY) / 64>(acc, part, SL_GAUSS_ABS_P, blk);
-    }
-}
-
-template <typename T>
-hipError_t launch_wind_gauss(const Geom &g, Fields<T> f, Moms<T> mom, T h, const double gcoef[2], uint8_t *wabs,
-                             uint32_t plane, int8_t *signed_out, Partials part, hipStream_t st) {
+hipError_t launch_cool(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, const StepCoef<T> &c, hipStream_t st) {
     dim3 block(BX, BY, 1);
     dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY, g.nz);
-    wind_gauss_kernel<T><<<grid, block, 0, st>>>(g, f, mom, h, gcoef[0], gcoef[1], wabs, plane, signed_out, part);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------ cells and overlap
-
-__global__ __launch_bounds__(BX *BY) void cells_kernel(Geom g, const uint8_t *wabs, uint8_t *cells, uint32_t plane) {
-    const int x = blockIdx.x * BX + threadIdx.x;
-    const int y = blockIdx.y * BY + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= g.nx || y >= g.ny) return;
-    const Site q = site_of(g, x, y, z);
-#pragma unroll
-    for (int sec = 0; sec < 2; sec++) {
-        const uint8_t *w = wabs + (size_t)sec * plane;
-        const uint32_t w0 = w[q.s];
-        const uint32_t n = (w0 & 3) + (w[q.xp] & 3) + ((w0 >> 2) & 3) + ((w[q.yp] >> 2) & 3) + ((w0 >> 4) & 3) +
-                           ((w[q.zp] >> 4) & 3);
-        cells[(size_t)sec * plane + q.s] = (uint8_t)n;
-    }
-}
-
-hipError_t launch_cells(const Geom &g, const uint8_t *wabs, uint8_t *cells, uint32_t plane, hipStream_t st) {
-    dim3 block(BX, BY, 1);
-    dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY, g.nz);
-    cells_kernel<<<grid, block, 0, st>>>(g, wabs, cells, plane);
-    return hipGetLastError();
-}
-
-__global__ __launch_bounds__(BX *BY) void overlap_kernel(Geom g, const uint8_t *cells, uint32_t plane, int radius,
-                                                         Partials part) {
-    const int x = blockIdx.x * BX + threadIdx.x;
-    const int y = blockIdx.y * BY + threadIdx.y;
-    const int z = blockIdx.z;
-    double acc[2] = {0, 0};
-    if (x < g.nx && y < g.ny) {
-        const uint32_t s = x + g.nx * y + g.nxy * z;
-#pragma unroll
-        for (int sec = 0; sec < 2; sec++) {
-            if (cells[(size_t)sec * plane + s] == 0) continue;
-            const uint8_t *o = cells + (size_t)(1 - sec) * plane;
-            bool hit = false;
-            for (int dz = -radius; dz <= radius && !hit; dz++) {
-                int zz = z + dz;
-                zz = zz < 0 ? zz + g.nz : (zz >= g.nz ? zz - g.nz : zz);
-                for (int dy = -radius; dy <= radius && !hit; dy++) {
-                    int yy = y + dy;
-                    yy = yy < 0 ? yy + g.ny : (yy >= g.ny ? yy - g.ny : yy);
-                    for (int dx = -radius; dx <= radius && !hit; dx++) {
-                        int xx = x + dx;
-                        xx = xx < 0 ? xx + g.nx : (xx >= g.nx ? xx - g.nx : xx);
-                        hit = o[xx + g.nx * yy + g.nxy * zz] != 0;
-                    }
-                }
-            }
-            acc[sec] = hit ? 1.0 : 0.0;
-        }
-    }
-    const uint32_t blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-    block_sum_store<2, (BX * BY) / 64>(acc, part, SL_OV_P, blk);
-}
-
-hipError_t launch_overlap(const Geom &g, const uint8_t *cells, uint32_t plane, int radius, Partials part,
-                          hipStream_t st) {
-    dim3 block(BX, BY, 1);
-    dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY, g.nz);
-    overlap_kernel<<<grid, block, 0, st>>>(g, cells, plane, radius, part);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------ final reduce
-
-// One block per slot; thread t sums partials t, t+256, ... in order, then a
-// fixed tree over the 256 threads.
-__global__ __launch_bounds__(256) void reduce_kernel(Partials part, const uint32_t *nblk, double *rec) {
-    __shared__ double red[256];
-    const int slot = blockIdx.x;
-    const uint32_t n = nblk[slot];
-    const double *p = part.base + (size_t)slot * part.maxblk;
-    double t = 0.0;
-    for (uint32_t i = threadIdx.x; i < n; i += 256) t += p[i];
-    red[threadIdx.x] = t;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) rec[slot] = red[0];
-}
-
-hipError_t launch_reduce(Partials part, const uint32_t *nblk_per_slot_dev, double *rec, hipStream_t st) {
-    reduce_kernel<<<NSLOT, 256, 0, st>>>(part, nblk_per_slot_dev, rec);
+    step_site_kernel<T, 2><<<grid, block, 0, st>>>(g, in, out, mom, c, Partials{nullptr, 0});
     return hipGetLastError();
 }
 
@@ -425,16 +261,45 @@ hipError_t launch_init(const Geom &g, Fields<T> f, Moms<T> mom, uint64_t seed, d
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ spot reads
+
+template <typename T>
+__global__ void gather_kernel(Fields<T> f, Moms<T> mom, const uint64_t *sites, int n, double *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t s = sites[i];
+    double *o = out + (size_t)i * 20;
+    for (int sec = 0; sec < 2; sec++) {
+        const cx<T> p = f.phi[sec][s], q = mom.pi[sec][s];
+        o[2 * sec] = p.re;
+        o[2 * sec + 1] = p.im;
+        o[4 + 2 * sec] = q.re;
+        o[5 + 2 * sec] = q.im;
+        for (int k = 0; k < 3; k++) {
+            o[8 + 3 * sec + k] = f.A[sec][k][s];
+            o[14 + 3 * sec + k] = mom.E[sec][k][s];
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_gather(Fields<T> f, Moms<T> mom, const uint64_t *sites, int n, double *out, hipStream_t st) {
+    gather_kernel<T><<<(n + 255) / 256, 256, 0, st>>>(f, mom, sites, n, out);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------ instantiations
 
 template hipError_t launch_step<float>(const Geom &, Fields<float>, Fields<float>, Moms<float>,
                                        const StepCoef<float> &, bool, Partials, hipStream_t);
 template hipError_t launch_step<double>(const Geom &, Fields<double>, Fields<double>, Moms<double>,
                                         const StepCoef<double> &, bool, Partials, hipStream_t);
-template hipError_t launch_wind_gauss<float>(const Geom &, Fields<float>, Moms<float>, float, const double[2],
-                                             uint8_t *, uint32_t, int8_t *, Partials, hipStream_t);
-template hipError_t launch_wind_gauss<double>(const Geom &, Fields<double>, Moms<double>, double, const double[2],
-                                              uint8_t *, uint32_t, int8_t *, Partials, hipStream_t);
+template hipError_t launch_cool<float>(const Geom &, Fields<float>, Fields<float>, Moms<float>,
+                                       const StepCoef<float> &, hipStream_t);
+template hipError_t launch_cool<double>(const Geom &, Fields<double>, Fields<double>, Moms<double>,
+                                        const StepCoef<double> &, hipStream_t);
+template hipError_t launch_gather<float>(Fields<float>, Moms<float>, const uint64_t *, int, double *, hipStream_t);
+template hipError_t launch_gather<double>(Fields<double>, Moms<double>, const uint64_t *, int, double *, hipStream_t);
 template hipError_t launch_init<float>(const Geom &, Fields<float>, Moms<float>, uint64_t, double, double,
                                        hipStream_t);
 template hipError_t launch_init<double>(const Geom &, Fields<double>, Moms<double>, uint64_t, double, double,

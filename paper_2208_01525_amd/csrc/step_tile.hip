@@ -203,11 +203,11 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                 cx<T> p1;
                 p1.re = c.cpi * p0[sec].re + c.kpi * F.re;
                 p1.im = c.cpi * p0[sec].im + c.kpi * F.im;
-                mom.pi[sec][s] = p1;
+                st_stream(&mom.pi[sec][s], p1);
                 cx<T> fn;
                 fn.re = f.re + c.k * p1.re;
                 fn.im = f.im + c.k * p1.im;
-                out.phi[sec][s] = fn;
+                st_stream(&out.phi[sec][s], fn);
 
                 const T sxy = sn[sec][0], sxz = sn[sec][1], syz = sn[sec][2];
                 const T sxy_my = L.v[sec][Q_SXY][lym], sxy_mx = L.v[sec][Q_SXY][lxm];
@@ -220,12 +220,12 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                 const T e1x = c.cE * e0[sec][0] + c.kE * (Mx + Jx);
                 const T e1y = c.cE * e0[sec][1] + c.kE * (My + Jy);
                 const T e1z = c.cE * e0[sec][2] + c.kE * (Mz + Jz);
-                mom.E[sec][0][s] = e1x;
-                mom.E[sec][1][s] = e1y;
-                mom.E[sec][2][s] = e1z;
-                out.A[sec][0][s] = cA[sec][0] + c.k * e1x;
-                out.A[sec][1][s] = cA[sec][1] + c.k * e1y;
-                out.A[sec][2][s] = cA[sec][2] + c.k * e1z;
+                st_stream(&mom.E[sec][0][s], e1x);
+                st_stream(&mom.E[sec][1][s], e1y);
+                st_stream(&mom.E[sec][2][s], e1z);
+                st_stream(&out.A[sec][0][s], cA[sec][0] + c.k * e1x);
+                st_stream(&out.A[sec][1][s], cA[sec][1] + c.k * e1y);
+                st_stream(&out.A[sec][2][s], cA[sec][2] + c.k * e1z);
 
                 if constexpr (DIAG) {
                     cx<T> pb;

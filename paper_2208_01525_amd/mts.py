@@ -17,8 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libmts.so")
 MTS_OK, MTS_EINVAL, MTS_EUNSTABLE, MTS_ENOMEM, MTS_EHIP, MTS_ENONFINITE = 0, -1, -2, -3, -4, -5
 MTS_FP32, MTS_FP64 = 1, 2
 
-EXPORTS = ("mts_state_bytes", "mts_create", "mts_destroy", "mts_init_fields", "mts_step", "mts_diagnostics",
-           "mts_get_fields", "mts_set_fields", "mts_get_windings", "mts_get_cells", "mts_set_tile", "mts_get_tile", "mts_autotune", "mts_timing_enable",
+EXPORTS = ("mts_state_bytes", "mts_create", "mts_destroy", "mts_init_fields", "mts_step", "mts_cool", "mts_diagnostics",
+           "mts_get_fields", "mts_set_fields", "mts_get_windings", "mts_get_cells", "mts_get_sites", "mts_segments", "mts_set_tile", "mts_get_tile", "mts_autotune", "mts_timing_enable",
            "mts_timing_read", "mts_last_error", "mts_strerror",
            "mts_batch_state_bytes", "mts_batch_create", "mts_batch_destroy", "mts_batch_size",
            "mts_batch_init_fields", "mts_batch_step", "mts_batch_diagnostics", "mts_batch_get_fields",
@@ -63,6 +63,15 @@ class Diag(ctypes.Structure):
         return out
 
 
+class Segments(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("marked_cells", ctypes.c_int64), ("regions", ctypes.c_int64),
+                ("n_pq", ctypes.c_int64), ("largest", ctypes.c_int64), ("L_pq", ctypes.c_double),
+                ("l_pq", ctypes.c_double), ("xi_pq", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class MtsError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{_strerror(code)}: {msg}")
@@ -87,11 +96,15 @@ def load():
     L.mts_destroy.argtypes = [vp]
     L.mts_init_fields.argtypes = [vp, ctypes.c_uint64]
     L.mts_step.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    L.mts_cool.argtypes = [vp, ctypes.c_int32, ctypes.c_double]
     L.mts_diagnostics.argtypes = [vp, ctypes.POINTER(Diag), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     L.mts_get_fields.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.mts_set_fields.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.mts_get_windings.argtypes = [vp, ctypes.POINTER(ctypes.c_int8)]
     L.mts_get_cells.argtypes = [vp, ctypes.POINTER(ctypes.c_uint8)]
+    L.mts_segments.argtypes = [vp, ctypes.c_double, ctypes.POINTER(Segments), ctypes.POINTER(ctypes.c_int64),
+                               ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    L.mts_get_sites.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
     L.mts_set_tile.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     L.mts_get_tile.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     i32p = ctypes.POINTER(ctypes.c_int32)
@@ -199,6 +212,9 @@ class Lattice:
     def step(self, n, eta, era_m, s):
         self._check(self.L.mts_step(self.ctx, int(n), float(eta), float(era_m), float(s)))
 
+    def cool(self, n, dt_cool=1.0 / 30.0):
+        self._check(self.L.mts_cool(self.ctx, int(n), float(dt_cool)))
+
     def diagnostics(self, max_records=8192, allow_nonfinite=False):
         buf = (Diag * max_records)()
         cnt = ctypes.c_int32()
@@ -217,6 +233,23 @@ class Lattice:
         host = np.ascontiguousarray(host, dtype=np.float64)
         assert host.shape == (20,) + self.shape
         self._check(self.L.mts_set_fields(self.ctx, host.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def get_sites(self, sites):
+        sites = np.ascontiguousarray(sites, dtype=np.uint64)
+        out = np.empty((len(sites), 20), dtype=np.float64)
+        self._check(self.L.mts_get_sites(self.ctx, sites.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), len(sites),
+                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def segments(self, min_length=0.0, max_sizes=1 << 20):
+        """Robust-method segments of the last diagnostic step: (summary dict, sizes)."""
+        out = Segments()
+        sizes = np.zeros(max_sizes, dtype=np.int64)
+        n = ctypes.c_int64()
+        self._check(self.L.mts_segments(self.ctx, float(min_length), ctypes.byref(out),
+                                        sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), max_sizes,
+                                        ctypes.byref(n)))
+        return out.as_dict(), sizes[:min(n.value, max_sizes)]
 
     def get_windings(self):
         out = np.empty((6,) + self.shape, dtype=np.int8)

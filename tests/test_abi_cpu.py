@@ -39,12 +39,15 @@ def test_struct_layout_matches_header():
     sizeof/offsetof with the ctypes mirrors."""
     fields_p = [f for f, _ in M.Params._fields_]
     fields_d = [f for f, _ in M.Diag._fields_]
+    fields_s = [f for f, _ in M.Segments._fields_]
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "mts.h"', "int main(void){"]
-    src.append('printf("%zu %zu\\n", sizeof(mts_params), sizeof(mts_diag));')
+    src.append('printf("%zu %zu %zu\\n", sizeof(mts_params), sizeof(mts_diag), sizeof(mts_segments_t));')
     for f in fields_p:
         src.append(f'printf("%zu\\n", offsetof(mts_params, {f}));')
     for f in fields_d:
         src.append(f'printf("%zu\\n", offsetof(mts_diag, {f}));')
+    for f in fields_s:
+        src.append(f'printf("%zu\\n", offsetof(mts_segments_t, {f}));')
     src.append("return 0;}")
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "probe.c")
@@ -54,9 +57,12 @@ def test_struct_layout_matches_header():
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
     vals = [int(v) for v in out]
     assert vals[0] == ctypes.sizeof(M.Params) and vals[1] == ctypes.sizeof(M.Diag)
-    offs = vals[2:]
-    assert offs[:len(fields_p)] == [getattr(M.Params, f).offset for f in fields_p]
-    assert offs[len(fields_p):] == [getattr(M.Diag, f).offset for f in fields_d]
+    assert vals[2] == ctypes.sizeof(M.Segments)
+    offs = vals[3:]
+    np_, nd = len(fields_p), len(fields_d)
+    assert offs[:np_] == [getattr(M.Params, f).offset for f in fields_p]
+    assert offs[np_:np_ + nd] == [getattr(M.Diag, f).offset for f in fields_d]
+    assert offs[np_ + nd:] == [getattr(M.Segments, f).offset for f in fields_s]
 
 
 def test_state_bytes():

@@ -133,8 +133,11 @@ def test_windings_bit_exact_on_identical_fields(precision):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("radius", [0, 1])
-def test_diagnostic_record_on_identical_inputs(precision, radius):
-    nx, ny, nz = 40, 18, 10
+@pytest.mark.parametrize("nx", [40, 64])
+def test_diagnostic_record_on_identical_inputs(precision, radius, nx):
+    """One diagnostic step on identical inputs; nx = 64 takes the packed-occupancy overlap
+    path, nx = 40 the per-cell one."""
+    ny, nz = 18, 10
     kw = dict(eta_ref=9.0, overlap_radius=radius, kappa=0.9)
     st = rounded(I.random_full(nx, ny, nz, 6, link=0.5, mom=0.5), precision)
     lat = lattice(nx, ny, nz, precision, diag_every=1, **kw)
@@ -335,3 +338,94 @@ def test_batch_boxes_match_single_contexts(precision):
             assert a["s"] == b["s"] and a["eta"] == pytest.approx(b["eta"], abs=1e-12)
     t = bt.timing_read()
     assert t["steps"] == n and t["ms"] > 0
+
+
+def _patch_sites(shape, centre, r=2):
+    nz, ny, nx = shape
+    z0, y0, x0 = centre
+    d = np.arange(-r, r + 1)
+    zz, yy, xx = np.meshgrid((z0 + d) % nz, (y0 + d) % ny, (x0 + d) % nx, indexing="ij")
+    return (xx + nx * (yy + ny * zz)).ravel().astype(np.uint64)
+
+
+def test_full_size_workload_sampled():
+    """The benchmarked configuration at its full size: 512^3, FP32, default tile, diagnostics
+    every 10 steps, radiation era with s = 1, seeded random phases.  After 10 steps, the 11th
+    (a diagnostic step) is checked at sampled sites -- tile corners and edges in x, y and z,
+    the box faces and random sites -- against the oracle's step on a 5^3 patch around each
+    site (the update at a site only reads its neighbours), and the windings there bit for bit.
+    The Gauss law and finiteness are checked over the whole box through the record."""
+    n = 512
+    lat = lattice(n, n, n, "fp32", eta_ref=128.0, diag_every=10)
+    assert lat.get_tile() == (8, 32)
+    lat.init_fields(1)
+    lat.step(10, 1.0, 0.5, 1.0)
+    rng = np.random.default_rng(7)
+    samples = [(0, 0, 0), (511, 511, 511), (31, 7, 63), (32, 8, 64), (33, 15, 127), (255, 256, 448), (96, 0, 511)]
+    samples += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(25)]
+    patches = [_patch_sites((n, n, n), c) for c in samples]
+    before = lat.get_sites(np.concatenate(patches))
+    W_all = lat.get_windings()
+    lat.step(1, 2.0, 0.5, 1.0)
+    rec = lat.diagnostics()
+    assert len(rec) == 2 and rec[-1]["step"] == 10
+    after = lat.get_sites(np.array([p[62] for p in patches], dtype=np.uint64))
+    m = O.model(5, eta_ref=128.0)
+    for k, c in enumerate(samples):
+        st = np.ascontiguousarray(before[125 * k:125 * (k + 1)].T.reshape(20, 5, 5, 5))
+        Wp = O.windings(m, st)
+        z0, y0, x0 = c
+        assert np.array_equal(Wp[:, 2, 2, 2], W_all[:, z0, y0, x0].astype(np.int32)), c
+        O.step(m, st, 2.0, 0.5, 1.0)
+        err = np.abs(st[:, 2, 2, 2] - after[k]).max()
+        assert err <= 64 * U["fp32"] * max(1.0, np.abs(st[:, 2, 2, 2]).max()), (c, err)
+    r = rec[-1]
+    assert all(np.isfinite([r["sum_energy"], r["sum_lagrangian"], r["sum_KL"], r["sum_GL"]]))
+    assert max(r["gauss_rel"]) < 2e-5
+    assert r["wind_abs"][0] == np.abs(W_all[:3]).sum() and r["wind_abs"][1] == np.abs(W_all[3:]).sum()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_cooling_parity(precision):
+    """Diffusive cooling (Sec. III) on the GPU against the oracle: 30 steps of 1/30 from
+    random phases and random links."""
+    nx, ny, nz = 40, 12, 9
+    st = I.random_phase(nx, ny, nz, 31)
+    st[I.A:I.A + 6] = I.random_full(nx, ny, nz, 32, link=0.4)[I.A:I.A + 6]
+    st = rounded(st, precision)
+    lat = lattice(nx, ny, nz, precision, eta_ref=4.0, kappa=0.9)
+    lat.set_fields(st)
+    lat.cool(30, 1.0 / 30.0)
+    got = lat.get_fields()
+    m = O.model(nx, ny, nz, kappa=0.9)
+    ref = st.copy()
+    O.cool(m, ref, 30, 1.0 / 30.0)
+    b = st * (1.0 + U[precision] * np.random.default_rng(0).choice([-1.0, 1.0], size=st.shape))
+    O.cool(m, b, 30, 1.0 / 30.0)
+    err = np.abs(got - ref).max()
+    assert err <= tolerance(np.abs(b - ref).max(), 30, ref, precision), err
+    with pytest.raises(P.MtsError) as e:
+        lat.cool(1, 0.1)          # 0.1 (48 + 3.8) > 2: forward Euler unstable
+    assert e.value.code == -2
+
+
+@pytest.mark.parametrize("radius", [0, 1])
+@pytest.mark.parametrize("geom,nsteps", [((40, 18, 12), 0), ((64, 16, 10), 0), ((64, 32, 24), 25)])
+def test_robust_segments_match_oracle(radius, geom, nsteps):
+    """Robust-method regions (GPU union-find) on identical cell arrays: the multiset of region
+    sizes equals the oracle's flood fill exactly; the kept segments and L_pq follow."""
+    nx, ny, nz = geom
+    lat = lattice(nx, ny, nz, "fp32", eta_ref=6.0, diag_every=1, overlap_radius=radius)
+    lat.init_fields(4)
+    if nsteps:
+        lat.step(nsteps, 1.0, 0.5, 1.0)
+    st = lat.get_fields()
+    lat.step(1, 1.0 + nsteps * 0.1, 0.5, 1.0)
+    summary, sizes = lat.segments(min_length=1.5)
+    m = O.model(nx, ny, nz, overlap_radius=radius)
+    ref = O.segments(m, O.cells(m, O.windings(m, st)))
+    assert list(sizes) == list(ref)
+    rob = O.robust(m, ref, 1.5)
+    assert summary["n_pq"] == rob["N_pq"] and summary["regions"] == len(ref)
+    assert summary["L_pq"] == pytest.approx(rob["L_pq"], rel=1e-12)
+    assert summary["marked_cells"] == int(ref.sum())

@@ -559,3 +559,116 @@ def test_velocity_estimator_on_exact_plane_waves():
         assert rec["sum_KL"] / rec["sum_GL"] == pytest.approx(R, rel=1e-9)
         assert rec["sum_KV"] / rec["sum_GV"] == pytest.approx(R, rel=1e-9)
         assert d["v2_pq"] == pytest.approx(2 * R / (1 + R), rel=1e-9)
+
+
+# --------------------------------------------------------------- diffusive cooling (Sec. III)
+
+
+def test_cooling_is_a_descending_flow():
+    """The cooling equations are the gradient flow of the static lattice energy (with kappa = 0):
+    every forward-Euler step of small size lowers it, the vacuum is a fixed point, and the
+    kappa coupling plays no part."""
+    nx = 8
+    m = O.model(nx, kappa=0.9)
+    st = I.random_phase(nx, nx, nx, 21)
+    st[I.A:I.A + 6] = I.random_full(nx, nx, nx, 22, link=0.3)[I.A:I.A + 6]
+    m0 = O.model(nx, kappa=0.0)
+    e = [O.hamiltonian(m0, st)]
+    for _ in range(40):
+        O.cool(m, st, 1, 1.0 / 30.0)
+        e.append(O.hamiltonian(m0, st))
+    assert all(b < a for a, b in zip(e, e[1:]))
+    assert e[-1] < 0.5 * e[0]
+    # kappa does not enter
+    s1, s2 = I.random_full(6, 5, 4, 3), None
+    s2 = s1.copy()
+    O.cool(O.model(6, 5, 4, kappa=0.9), s1, 5)
+    O.cool(O.model(6, 5, 4, kappa=0.0), s2, 5)
+    assert np.array_equal(s1, s2)
+    # momenta untouched, vacuum fixed
+    assert np.array_equal(s1[4:8], I.random_full(6, 5, 4, 3)[4:8])
+    vac = I.empty(5, 5, 5)
+    vac[I.PHI] = vac[I.PSI] = 1.0
+    ref = vac.copy()
+    O.cool(O.model(5), vac, 10)
+    assert np.array_equal(vac, ref)
+
+
+def test_cooling_step_is_forward_euler_of_the_forces():
+    """One cooling step moves phi and A by dt times the update's own forces at a = 1, kappa = 0."""
+    m = O.model(6, 5, 7, kappa=0.0)
+    st = I.random_full(6, 5, 7, 9)
+    F = O.forces(m, st, 1.0)
+    ref = st.copy()
+    ref[0:4] += 0.03 * F[0:4]
+    ref[8:14] += 0.03 * F[4:10]
+    O.cool(O.model(6, 5, 7, kappa=0.4), st, 1, 0.03)
+    assert np.abs(st - ref).max() < 1e-14
+
+
+# --------------------------------------------------------------- robust-method segments
+
+
+def _py_components(mark):
+    """Brute force: union-find over every pair of marked cells within one cell
+    (periodic Chebyshev distance <= 1), in plain Python."""
+    nz, ny, nx = mark.shape
+    cells = [tuple(c) for c in np.argwhere(mark)]
+    idx = {c: i for i, c in enumerate(cells)}
+    parent = list(range(len(cells)))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for (z, y, x), i in idx.items():
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    j = idx.get(((z + dz) % nz, (y + dy) % ny, (x + dx) % nx))
+                    if j is not None:
+                        ra, rb = find(i), find(j)
+                        if ra != rb:
+                            parent[ra] = rb
+    sizes = {}
+    for i in range(len(cells)):
+        r = find(i)
+        sizes[r] = sizes.get(r, 0) + 1
+    return sorted(sizes.values(), reverse=True)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_segments_match_brute_force(seed):
+    """Connected regions of pq cells on random sparse cell arrays, against a Python
+    union-find over all neighbouring pairs (periodic, 26-neighbourhood)."""
+    nx, ny, nz = 11, 9, 8
+    m = O.model(nx, ny, nz)
+    rng = np.random.default_rng(seed)
+    n = (rng.random((2, nz, ny, nx)) < 0.12).astype(np.int32) * 2
+    mark = np.zeros((nz, ny, nx), dtype=bool)
+    for sec in range(2):
+        other = n[1 - sec] > 0
+        dil = np.zeros_like(other)
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    dil |= np.roll(other, (dz, dy, dx), axis=(0, 1, 2))
+        mark |= (n[sec] > 0) & dil
+    got = O.segments(m, n)
+    assert list(got) == _py_components(mark)
+    assert got.sum() == mark.sum()
+
+
+def test_segments_of_bound_string_pairs():
+    """A bound straight pair (p and q strings coincident or one cell apart) gives one region
+    per string, each threading the box (N_z cells); two cells apart there is none."""
+    nx, ny, nz = 20, 14, 9
+    m = O.model(nx, ny, nz)
+    for dx, expect in ((0, [nz, nz]), (1, [2 * nz, 2 * nz]), (2, [])):
+        st = I.string_pairs(nx, ny, nz, p_pair=(5, 12, 7), q_pair=(5 + dx, 12 + dx, 7))
+        sizes = O.segments(m, O.cells(m, O.windings(m, st)))
+        assert list(sizes) == expect, dx
+    r = O.robust(m, [2 * nz, 2 * nz, 3], min_length=2.0)
+    assert r["N_pq"] == 2 and r["L_pq"] == 2 * (2 * nz - 1) * 0.5

@@ -26,12 +26,44 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_SITE = {"fp32": 160, "fp64": 320}   # 20 reals read + 20 written per site-update
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_tile_512.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2208_01525_amd", "csrc", f) for f in ("step_tile.hip", "device.h", "kernels.h")]
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(n, precision, tile, nt):
+    """HBM bytes per launch of the update kernel from the committed rocprofv3
+    counter summary, if it was taken on this kernel source, tile shape, store
+    mode and workload; else None."""
+    if n != 512 or precision != "fp32" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = dict(l.strip().split("=", 1) for l in open(TRAFFIC_FILE) if "=" in l and not l.startswith("#"))
+    if kv.get("source_sha256") != kernel_source_hash() or kv.get("tile") != f"{tile[0]},{tile[1]}":
+        return None
+    if kv.get("streaming_stores") != str(int(nt)):
+        return None
+    return int(kv["bytes_per_launch"])
+
+
 def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0.5, s=1.0, eta_ref=128.0, seed=1,
             tile=None):
     params = P.make_params(n, precision=precision, eta_ref=eta_ref, diag_every=diag_every)
     lat = P.Lattice(params, device="cuda:0")
+    tuned = None
     if tile is not None:
-        lat.set_tile(*tile)
+        lat.set_tile(*tile[:2])
+        if len(tile) > 2:
+            lat.set_streaming_stores(bool(tile[2]))
+    else:
+        tuned = lat.autotune(4)      # times every tile shape on this box (leaves seed-0 fields)
     lat.init_fields(seed)
     lat.step(warmup, eta0, era_m, s)
     lat.diagnostics()
@@ -57,8 +89,12 @@ def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0
         "diag_step_kernel_ms": tm["ms_diag"] / max(tm["n_diag"], 1),
         "diag_post_ms": tm["ms_post"] / max(tm["n_diag"], 1),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(n, precision, lat.get_tile(), lat.get_streaming_stores()),
+                     "algorithmic_bytes": BYTES_PER_SITE[precision] * sites},
         "tile": lat.get_tile(),
+        "streaming_stores": lat.get_streaming_stores(),
+        "autotune_ms_per_step": tuned[2] if tuned else None,
         "last_record": {k: recs[-1][k] for k in ("eta", "xi_W", "xi_lag", "v2_lag", "f_total", "gauss_rel")}
         if recs else None,
     }
@@ -94,7 +130,8 @@ def run_batch(P, torch, steps, small=48, big=16, tune_steps=3):
     achieved = BYTES_PER_SITE["fp32"] * sites * steps / (tm["ms"] * 1e-3) / 1e9
     out = {"value": sites * steps / wall, "unit": "site-updates/s", "boxes": f"{small}x128^3 + {big}x256^3",
            "sites": sites, "steps": steps, "ms_per_step": 1e3 * wall / steps, "graph_ms": tm["ms"],
-           "tile": [ty, tz], "autotune_ms_per_step": tune_ms, "records_per_box": min(nrec),
+           "tile": [ty, tz], "streaming_stores": bt.get_streaming_stores(), "autotune_ms_per_step": tune_ms,
+           "records_per_box": min(nrec),
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                         "note": "whole graph time, diagnostic kernels included"}}
@@ -146,8 +183,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=400)
     ap.add_argument("--copy-probe", action="store_true", help="only time a plain copy (counter calibration)")
-    ap.add_argument("--tile", type=str, default=None, help="ty,tz of the update kernel (0,1: per-site kernel)")
+    ap.add_argument("--source-hash", action="store_true", help="print the update kernel's source hash")
+    ap.add_argument("--tile", type=str, default=None,
+                    help="ty,tz[,nt] of the update kernel (0,1: per-site kernel; nt 1/0: streaming or plain stores)")
     args = ap.parse_args()
+    if args.source_hash:
+        print(kernel_source_hash())
+        return
     if args.gpus != 1:
         print("bench.py: this implementation runs on one GPU only (the lattice is not sharded); "
               "use --gpus 1", file=sys.stderr)
@@ -196,11 +238,12 @@ def main():
         "cpu_baseline": cpu,
         "kernel_ms": fp32["kernel_ms"],
         "tile": fp32["tile"],
+        "streaming_stores": fp32["streaming_stores"],
         "diag_step_kernel_ms": fp32["diag_step_kernel_ms"],
         "diag_post_ms": fp32["diag_post_ms"],
         "fp64": {"value": fp64["value"], "unit": "site-updates/s", "steps": args.fp64_steps,
-                 "ms_per_step": fp64["ms_per_step"], "kernel_ms": fp64["kernel_ms"],
-                 "roofline": fp64["roofline"]} if fp64 else None,
+                 "ms_per_step": fp64["ms_per_step"], "kernel_ms": fp64["kernel_ms"], "tile": fp64["tile"],
+                 "streaming_stores": fp64["streaming_stores"], "roofline": fp64["roofline"]} if fp64 else None,
         "batch": batch,
         "last_record": fp32["last_record"],
     }

@@ -212,16 +212,25 @@ int mts_segments(mts_ctx *ctx, double min_length, mts_segments_t *out, int64_t *
 
 /* Choose the update kernel.  ty in {4, 8, 12} selects the z-marching
  * LDS-tiled kernel with tiles of 64 x ty sites and tz >= 1 planes per
- * workgroup (default 8 x 32 in FP32, 4 x 32 in FP64); every tile shape
- * gives bitwise identical
+ * workgroup (default 8 x 32 in FP32, 4 x 32 in FP64; diagnostic steps use
+ * at most 8 rows in FP32 and 4 in FP64, where their variant does not
+ * spill registers); every tile shape gives bitwise identical
  * results.  ty = 0 selects the one-thread-per-site kernel, which computes
  * the plaquette sines directly and agrees with the tiled kernel to
  * rounding.  Synchronises the stream.  EINVAL for other shapes. */
 int mts_set_tile(mts_ctx *ctx, int32_t ty, int32_t tz);
 int mts_get_tile(const mts_ctx *ctx, int32_t *ty, int32_t *tz);
 
+/* Streaming (non-temporal) stores for the tiled update's outputs: on (1,
+ * the default of a single box) or off (0, the default of a batch).  Which
+ * is faster depends on the launch; results are bitwise identical.  The
+ * autotuners try both. */
+int mts_set_streaming_stores(mts_ctx *ctx, int32_t on);
+int mts_get_streaming_stores(const mts_ctx *ctx, int32_t *on);
+
 /* Autotuner: time `steps` plain steps of every supported tile shape
- * (ty in {4, 8, 12} -- {4, 8} in FP64 -- by tz in {8, 16, 32, 64}) on this
+ * (ty in {4, 8, 12} -- {4, 8} in FP64 -- by tz in {8, 16, 32, 64}, with and
+ * without streaming stores) on this
  * box with HIP events, keep the fastest, and report it (and its ms per
  * step).  The choice changes speed only: results are bitwise identical for
  * every shape.  Overwrites the lattice (it is left at seed-0 initial
@@ -281,6 +290,8 @@ int mts_batch_set_fields(mts_batch *b, int32_t box, const double *host);
 /* Tile shape of the batched launch: one ty in {4, 8, 12} for all boxes and
  * a tz[nbox] per box. */
 int mts_batch_set_tile(mts_batch *b, int32_t ty, const int32_t *tz);
+int mts_batch_set_streaming_stores(mts_batch *b, int32_t on);
+int mts_batch_get_streaming_stores(const mts_batch *b, int32_t *on);
 
 /* Summed HIP-event time (ms) of the graph launches and the steps they ran
  * since the last read; synchronises. */

@@ -40,6 +40,7 @@ struct mts_ctx {
     uint32_t maxblk = 0;
     uint32_t *nblk_dev = nullptr;
     TileShape tile{8, 32};       // ty = 0: per-site kernel
+    bool nt = true;              // streaming stores in the tiled update
     void *alpha = nullptr;       // arg(phi) per sector: T[2][plane]
     uint8_t *wabs = nullptr;     // packed |W| per sector: [2][plane]
     uint8_t *cells = nullptr;    // cell values per sector: [2][plane]
@@ -206,11 +207,20 @@ struct TimedRegion {
     }
 };
 
+// Diagnostic steps use the DIAG variant of the update kernel, which needs
+// more registers: it runs with at most 8 (FP32) or 4 (FP64) rows per tile so
+// that it never spills.  Tile shapes do not change results (bitwise).
+TileShape diag_tile(const mts_ctx *c) {
+    if (c->tile.ty == 0) return c->tile;
+    const int cap = c->p.precision == MTS_FP64 ? 4 : 8;
+    return TileShape{std::min(c->tile.ty, cap), c->tile.tz};
+}
+
 // Partials per slot: the update kernel's blocks for the integer-time sums,
 // the per-site grid for the post-step diagnostic kernels.
 hipError_t upload_nblk(mts_ctx *c) {
     uint32_t nb[NSLOT];
-    const uint32_t step_blocks = c->tile.ty == 0 ? site_blocks(c->g) : tile_blocks(c->g, c->tile);
+    const uint32_t step_blocks = c->tile.ty == 0 ? site_blocks(c->g) : tile_blocks(c->g, diag_tile(c));
     for (int q = 0; q < NSLOT; q++)
         nb[q] = q <= SL_GV ? step_blocks : (q <= SL_WIND_Q ? wind_blocks(c->g) : (q <= SL_OV_Q ? overlap_blocks(c->g) : 0));
     return hipMemcpy(c->nblk_dev, nb, sizeof(nb), hipMemcpyHostToDevice);
@@ -220,14 +230,14 @@ hipError_t upload_nblk(mts_ctx *c) {
 // reduce into the next ring slot) for the step from eta_j; fields at n are
 // in copy `cur`.  Host-side facts of the record are queued.
 template <typename T>
-hipError_t enqueue_diag_post(mts_ctx *c, const Book &b, double eta_j, double s, hipStream_t st) {
+hipError_t enqueue_diag_post(mts_ctx *c, const Book &b, double eta_j, double s, hipStream_t st, bool alpha_ready) {
     const mts_params &p = c->p;
     Partials part{c->partials, c->maxblk};
     double gcoef[2];
     const double e2[2] = {p.e_p * p.e_p, p.e_q * p.e_q};
     for (int q = 0; q < 2; q++) gcoef[q] = 2.0 * e2[q] * b.An * (1.0 + b.delta) / (1.0 + b.omega);
     T *alpha = static_cast<T *>(c->alpha);
-    hipError_t e = launch_phase<T>(c->g, fields_of<T>(c, c->cur), alpha, (uint32_t)c->plane, st);
+    hipError_t e = alpha_ready ? hipSuccess : launch_phase<T>(c->g, fields_of<T>(c, c->cur), alpha, (uint32_t)c->plane, st);
     if (e == hipSuccess)
         e = launch_wind_gauss<T>(c->g, fields_of<T>(c, c->cur), moms_of<T>(c), alpha, (T)p.dx, gcoef, c->wabs,
                                  (uint32_t)c->plane, nullptr, part, st);
@@ -257,14 +267,17 @@ int do_step(mts_ctx *c, int32_t n, double eta, double era_m, double s) {
         Fields<T> in = fields_of<T>(c, c->cur), out = fields_of<T>(c, 1 - c->cur);
         {
             TimedRegion tr(c, diag ? 1 : 0);
-            hipError_t e = c->tile.ty == 0 ? launch_step<T>(c->g, in, out, mom, coef, diag, part, c->stream)
-                                           : launch_step_tile<T>(c->g, in, out, mom, coef, diag, part, c->tile,
-                                                                 c->stream);
+            hipError_t e = c->tile.ty == 0
+                               ? launch_step<T>(c->g, in, out, mom, coef, diag, part, c->stream)
+                               : launch_step_tile<T>(c->g, in, out, mom, coef, diag, part,
+                                                     diag ? diag_tile(c) : c->tile,
+                                                     static_cast<T *>(c->alpha), (uint32_t)c->plane, c->nt,
+                                                     c->stream);
             if (e != hipSuccess) return hipfail(c, e, "step kernel launch");
         }
         if (diag) {
             TimedRegion tr(c, 2);
-            hipError_t e = enqueue_diag_post<T>(c, b, eta_j, s, c->stream);
+            hipError_t e = enqueue_diag_post<T>(c, b, eta_j, s, c->stream, c->tile.ty != 0);
             if (e != hipSuccess) return hipfail(c, e, "diagnostic kernel launch");
         }
         c->cur = 1 - c->cur;
@@ -691,6 +704,19 @@ int mts_set_tile(mts_ctx *c, int32_t ty, int32_t tz) {
     return MTS_OK;
 }
 
+int mts_set_streaming_stores(mts_ctx *c, int32_t on) {
+    if (!c) return MTS_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->nt = on != 0;
+    return MTS_OK;
+}
+
+int mts_get_streaming_stores(const mts_ctx *c, int32_t *on) {
+    if (!c || !on) return MTS_EINVAL;
+    *on = c->nt ? 1 : 0;
+    return MTS_OK;
+}
+
 int mts_get_tile(const mts_ctx *c, int32_t *ty, int32_t *tz) {
     if (!c || !ty || !tz) return MTS_EINVAL;
     *ty = c->tile.ty;
@@ -709,11 +735,14 @@ int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, do
     HIPCHK(c, hipEventCreate(&e1));
     double best = INFINITY;
     TileShape pick = c->tile;
+    bool pick_nt = c->nt;
     int rc = mts_init_fields(c, 0);
+    for (int nt = 0; nt < 2; nt++)
     for (int ty : tys) {
         for (int tz : tzs) {
             if (rc != MTS_OK) break;
             if (tz > 2 * c->p.nz && tz != 8) continue;
+            c->nt = nt != 0;
             if ((rc = mts_set_tile(c, ty, tz)) != MTS_OK) break;
             if ((rc = mts_step(c, 1, 1.0, 0.5, 1.0)) != MTS_OK) break;       // warm
             HIPCHK(c, hipEventRecord(e0, c->stream));
@@ -725,9 +754,11 @@ int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, do
             if (ms < best) {
                 best = ms;
                 pick = TileShape{ty, tz};
+                pick_nt = nt != 0;
             }
         }
     }
+    c->nt = pick_nt;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->p.diag_every = d;
@@ -796,7 +827,11 @@ struct mts_batch {
     hipStream_t user = nullptr;      // caller's stream
     hipStream_t stream = nullptr;    // internal stream the graphs are captured on and launched to
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
-    void *boxes_dev = nullptr;       // BatchBox<T>[nbox]
+    void *boxes_dev = nullptr;       // BatchBox<T>[nbox] for plain steps
+    void *boxes_diag_dev = nullptr;  // BatchBox<T>[nbox] for diagnostic steps (their own tile rows)
+    int32_t ty_diag = 8;
+    uint32_t nblk_diag = 0;
+    bool nt = false;                 // plain stores: measured faster for ensembles of small boxes
     void *coef_dev = nullptr;        // StepCoef<T>[n][nbox]
     size_t coef_cap = 0;             // bytes
     int32_t ty = 8;
@@ -828,28 +863,38 @@ size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 template <typename T>
 int batch_upload_boxes(mts_batch *b) {
-    std::vector<BatchBox<T>> h(b->box.size());
-    uint32_t blk = 0;
-    for (size_t k = 0; k < b->box.size(); k++) {
+    const size_t nbox = b->box.size();
+    std::vector<BatchBox<T>> h(nbox), hd(nbox);
+    uint32_t blk = 0, blkd = 0;
+    for (size_t k = 0; k < nbox; k++) {
         mts_ctx *c = b->box[k];
-        BatchBox<T> &x = h[k];
-        x.g = c->g;
-        x.f[0] = fields_of<T>(c, 0);
-        x.f[1] = fields_of<T>(c, 1);
-        x.mom = moms_of<T>(c);
-        x.part = Partials{c->partials, c->maxblk};
-        x.tz = b->tz[k];
-        x.ntx = (c->g.nx + 63) / 64;
-        x.nty = (c->g.ny + b->ty - 1) / b->ty;
-        x.ntz = (c->g.nz + x.tz - 1) / x.tz;
-        x.blk0 = blk;
-        blk += (uint32_t)(x.ntx * x.nty * x.ntz);
-        c->tile = TileShape{b->ty, x.tz};
+        c->tile = TileShape{b->ty, b->tz[k]};
+        b->ty_diag = diag_tile(c).ty;
+        for (int pass = 0; pass < 2; pass++) {
+            BatchBox<T> &x = pass == 0 ? h[k] : hd[k];
+            const int ty = pass == 0 ? b->ty : b->ty_diag;
+            uint32_t &acc = pass == 0 ? blk : blkd;
+            x.g = c->g;
+            x.f[0] = fields_of<T>(c, 0);
+            x.f[1] = fields_of<T>(c, 1);
+            x.mom = moms_of<T>(c);
+            x.part = Partials{c->partials, c->maxblk};
+            x.alpha = static_cast<T *>(c->alpha);
+            x.plane = (uint32_t)c->plane;
+            x.tz = b->tz[k];
+            x.ntx = (c->g.nx + 63) / 64;
+            x.nty = (c->g.ny + ty - 1) / ty;
+            x.ntz = (c->g.nz + x.tz - 1) / x.tz;
+            x.blk0 = acc;
+            acc += (uint32_t)(x.ntx * x.nty * x.ntz);
+        }
         hipError_t e = upload_nblk(c);
         if (e != hipSuccess) return bfail(b, MTS_EHIP, std::string("upload_nblk: ") + hipGetErrorString(e));
     }
     b->nblk = blk;
-    BHIPCHK(b, hipMemcpy(b->boxes_dev, h.data(), sizeof(BatchBox<T>) * h.size(), hipMemcpyHostToDevice));
+    b->nblk_diag = blkd;
+    BHIPCHK(b, hipMemcpy(b->boxes_dev, h.data(), sizeof(BatchBox<T>) * nbox, hipMemcpyHostToDevice));
+    BHIPCHK(b, hipMemcpy(b->boxes_diag_dev, hd.data(), sizeof(BatchBox<T>) * nbox, hipMemcpyHostToDevice));
     return MTS_OK;
 }
 
@@ -918,13 +963,14 @@ int batch_step_t(mts_batch *b, int32_t n, const double *eta0, const double *era_
     for (int32_t j = 0; j < n && err == hipSuccess; j++) {
         mts_ctx *c0 = b->box[0];
         const bool diag = d > 0 && (c0->step_count % d) == 0;
-        err = launch_step_tile_batch<T>(static_cast<const BatchBox<T> *>(b->boxes_dev), (int)nbox, b->nblk, c0->cur,
-                                        static_cast<const StepCoef<T> *>(b->coef_dev) + (size_t)j * nbox, diag, b->ty,
-                                        b->stream);
+        err = launch_step_tile_batch<T>(static_cast<const BatchBox<T> *>(diag ? b->boxes_diag_dev : b->boxes_dev),
+                                        (int)nbox, diag ? b->nblk_diag : b->nblk, c0->cur,
+                                        static_cast<const StepCoef<T> *>(b->coef_dev) + (size_t)j * nbox, diag,
+                                        diag ? b->ty_diag : b->ty, b->nt, b->stream);
         if (diag)
             for (size_t k = 0; k < nbox && err == hipSuccess; k++)
                 err = enqueue_diag_post<T>(b->box[k], books[k][j], eta0[k] + j * b->box[k]->p.dt, svals[k][j],
-                                           b->stream);
+                                           b->stream, true);
         for (mts_ctx *c : b->box) {
             c->cur = 1 - c->cur;
             c->step_count++;
@@ -1002,6 +1048,7 @@ int mts_batch_create(const mts_params *boxes, int32_t nbox, void *dev_pool, size
     if (rc == MTS_OK && e == hipSuccess) {
         const size_t bb = (b->precision == MTS_FP64 ? sizeof(BatchBox<double>) : sizeof(BatchBox<float>)) * nbox;
         e = hipMalloc(&b->boxes_dev, bb);
+        if (e == hipSuccess) e = hipMalloc(&b->boxes_diag_dev, bb);
     }
     if (rc == MTS_OK && e != hipSuccess) rc = MTS_ENOMEM;
     if (rc == MTS_OK) rc = batch_upload(b);
@@ -1020,6 +1067,7 @@ int mts_batch_destroy(mts_batch *b) {
     batch_release_graph(b);
     for (mts_ctx *c : b->box) mts_destroy(c);
     (void)hipFree(b->boxes_dev);
+    (void)hipFree(b->boxes_diag_dev);
     (void)hipFree(b->coef_dev);
     for (hipEvent_t ev : {b->ev_in, b->ev_out, b->ev_t0, b->ev_t1})
         if (ev) (void)hipEventDestroy(ev);
@@ -1083,6 +1131,19 @@ int mts_batch_set_tile(mts_batch *b, int32_t ty, const int32_t *tz) {
     return batch_upload(b);
 }
 
+int mts_batch_set_streaming_stores(mts_batch *b, int32_t on) {
+    if (!b) return MTS_EINVAL;
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    b->nt = on != 0;
+    return MTS_OK;
+}
+
+int mts_batch_get_streaming_stores(const mts_batch *b, int32_t *on) {
+    if (!b || !on) return MTS_EINVAL;
+    *on = b->nt ? 1 : 0;
+    return MTS_OK;
+}
+
 int mts_batch_timing_read(mts_batch *b, int64_t *steps, double *ms) {
     if (!b) return MTS_EINVAL;
     BHIPCHK(b, hipStreamSynchronize(b->stream));
@@ -1109,12 +1170,15 @@ int mts_batch_autotune(mts_batch *b, int32_t steps, int32_t *ty_out, int32_t *tz
     int rc = mts_batch_init_fields(b, seeds.data());
     double best = INFINITY;
     int pick_ty = b->ty, pick_tz = b->tz.empty() ? 32 : b->tz[0];
+    bool pick_nt = b->nt;
     int nzmax = 0;
     for (mts_ctx *c : b->box) nzmax = std::max(nzmax, c->p.nz);
+    for (int nt = 0; nt < 2; nt++)
     for (int ty : tys)
         for (int tz : tzs) {
             if (rc != MTS_OK) break;
             if (tz > 2 * nzmax && tz != 8) continue;
+            b->nt = nt != 0;
             std::vector<int32_t> tzv(nbox, tz);
             if ((rc = mts_batch_set_tile(b, ty, tzv.data())) != MTS_OK) break;
             if ((rc = mts_batch_step(b, 1, eta.data(), era.data(), sv.data(), nullptr, nullptr)) != MTS_OK) break;
@@ -1127,8 +1191,10 @@ int mts_batch_autotune(mts_batch *b, int32_t steps, int32_t *ty_out, int32_t *tz
                 best = ms;
                 pick_ty = ty;
                 pick_tz = tz;
+                pick_nt = nt != 0;
             }
         }
+    b->nt = pick_nt;
     for (size_t k = 0; k < nbox; k++) b->box[k]->p.diag_every = d[k];
     if (rc != MTS_OK) return rc;
     std::vector<int32_t> tzv(nbox, pick_tz);

@@ -48,18 +48,27 @@ struct Pi<double> {
     static constexpr double v = 3.14159265358979323846;
 };
 
-// Streaming (non-temporal) stores for data written once per step and not
-// re-read by this launch: they bypass L2 allocation, leaving L2 to the
-// halo rows that neighbouring tiles share.
-template <typename T>
+// Stores of data written once per step and not re-read by this launch.
+// With NT they are streaming (non-temporal) stores that bypass L2
+// allocation, leaving L2 to the halo rows neighbouring tiles share; which
+// mode is faster depends on the launch (measured: streaming helps a single
+// large box, plain stores an ensemble of small ones), so it is tunable.
+template <bool NT, typename T>
 __device__ __forceinline__ void st_stream(T *p, T v) {
-    __builtin_nontemporal_store(v, p);
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
 }
-template <typename T>
+template <bool NT, typename T>
 __device__ __forceinline__ void st_stream(cx<T> *p, cx<T> v) {
-    typedef T v2 __attribute__((ext_vector_type(2)));
-    v2 w = {v.re, v.im};
-    __builtin_nontemporal_store(w, reinterpret_cast<v2 *>(p));
+    if constexpr (NT) {
+        typedef T v2 __attribute__((ext_vector_type(2)));
+        v2 w = {v.re, v.im};
+        __builtin_nontemporal_store(w, reinterpret_cast<v2 *>(p));
+    } else {
+        *p = v;
+    }
 }
 
 // link phasor exp(-i h A)

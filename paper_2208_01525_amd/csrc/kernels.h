@@ -89,9 +89,13 @@ struct TileShape {
 };
 bool tile_supported(TileShape ts);
 uint32_t tile_blocks(const Geom &g, TileShape ts);
+// With diag it also writes the phase arg(phi^n) of every site into
+// alpha[2][plane] (NaN where phi = 0), the winding kernel's input.
+// nt selects streaming (non-temporal) stores for the outputs.
 template <typename T>
 hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, const StepCoef<T> &c,
-                            bool diag, Partials part, TileShape ts, hipStream_t st);
+                            bool diag, Partials part, TileShape ts, T *alpha, uint32_t plane, bool nt,
+                            hipStream_t st);
 
 // One box of an ensemble advanced by a single launch.
 template <typename T>
@@ -100,12 +104,14 @@ struct BatchBox {
     Fields<T> f[2];       // field copies 0 and 1
     Moms<T> mom;
     Partials part;        // this box's partials (box-local block index)
+    T *alpha;             // this box's phase scratch [2][plane]
+    uint32_t plane;
     int32_t ntx, nty, ntz, tz;
     uint32_t blk0;        // first block of this box in the launch
 };
 template <typename T>
 hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32_t nblk, int parity,
-                                  const StepCoef<T> *coef_dev, bool diag, int ty, hipStream_t st);
+                                  const StepCoef<T> *coef_dev, bool diag, int ty, bool nt, hipStream_t st);
 
 // Phase alpha = arg(phi) of every site and sector into alpha[2][plane]
 // (NaN where phi = 0), input of the winding kernel.

@@ -58,10 +58,10 @@ __device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t nblk) {
 
 // One tile (64 x TY columns, planes [Z0, Z0 + TZ)) of one box; accumulates the
 // integer-time sums of its interior sites into acc when DIAG.
-template <typename T, bool DIAG, int TY>
+template <typename T, bool DIAG, int TY, bool NT>
 __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, const Fields<T> &out,
                                           const Moms<T> &mom, const StepCoef<T> &c, int X0, int Y0, int Z0, int TZ,
-                                          Lds<T, TY> &L, double (&acc)[6]) {
+                                          Lds<T, TY> &L, double (&acc)[6], T *alpha, uint32_t plane) {
     constexpr int R = TY + 2;
 
     // ---- which site of the tile this thread holds
@@ -203,11 +203,11 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                 cx<T> p1;
                 p1.re = c.cpi * p0[sec].re + c.kpi * F.re;
                 p1.im = c.cpi * p0[sec].im + c.kpi * F.im;
-                st_stream(&mom.pi[sec][s], p1);
+                st_stream<NT>(&mom.pi[sec][s], p1);
                 cx<T> fn;
                 fn.re = f.re + c.k * p1.re;
                 fn.im = f.im + c.k * p1.im;
-                st_stream(&out.phi[sec][s], fn);
+                st_stream<NT>(&out.phi[sec][s], fn);
 
                 const T sxy = sn[sec][0], sxz = sn[sec][1], syz = sn[sec][2];
                 const T sxy_my = L.v[sec][Q_SXY][lym], sxy_mx = L.v[sec][Q_SXY][lxm];
@@ -220,12 +220,12 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                 const T e1x = c.cE * e0[sec][0] + c.kE * (Mx + Jx);
                 const T e1y = c.cE * e0[sec][1] + c.kE * (My + Jy);
                 const T e1z = c.cE * e0[sec][2] + c.kE * (Mz + Jz);
-                st_stream(&mom.E[sec][0][s], e1x);
-                st_stream(&mom.E[sec][1][s], e1y);
-                st_stream(&mom.E[sec][2][s], e1z);
-                st_stream(&out.A[sec][0][s], cA[sec][0] + c.k * e1x);
-                st_stream(&out.A[sec][1][s], cA[sec][1] + c.k * e1y);
-                st_stream(&out.A[sec][2][s], cA[sec][2] + c.k * e1z);
+                st_stream<NT>(&mom.E[sec][0][s], e1x);
+                st_stream<NT>(&mom.E[sec][1][s], e1y);
+                st_stream<NT>(&mom.E[sec][2][s], e1z);
+                st_stream<NT>(&out.A[sec][0][s], cA[sec][0] + c.k * e1x);
+                st_stream<NT>(&out.A[sec][1][s], cA[sec][1] + c.k * e1y);
+                st_stream<NT>(&out.A[sec][2][s], cA[sec][2] + c.k * e1z);
 
                 if constexpr (DIAG) {
                     cx<T> pb;
@@ -245,6 +245,13 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                 }
             }
             if constexpr (DIAG) {
+                // phase of phi^n for the winding kernel (NaN where phi = 0)
+#pragma unroll
+                for (int sec = 0; sec < 2; sec++) {
+                    const cx<T> f = cf[sec];
+                    const T al = (f.re == T(0) && f.im == T(0)) ? T(NAN) : atan2_t(f.im, f.re);
+                    st_stream<NT>(alpha + (size_t)sec * plane + s, al);
+                }
                 const T dp = mod2[0] - c.sig2[0], dq = mod2[1] - c.sig2[1];
                 const T Vint = c.kap0 * dp * dq;
                 const T V = (c.lam4[0] * dp * dp + c.lam4[1] * dq * dq) - Vint;
@@ -278,22 +285,22 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
     }
 }
 
-template <typename T, bool DIAG, int TY>
+template <typename T, bool DIAG, int TY, bool NT>
 __global__ __launch_bounds__(64 * (TY + 3)) void step_tile_kernel(Geom g, Fields<T> in, Fields<T> out, Moms<T> mom,
                                                                   StepCoef<T> c, Partials part, int TZ, int ntx,
-                                                                  int nty, int ntz) {
+                                                                  int nty, int ntz, T *alpha, uint32_t plane) {
     __shared__ Lds<T, TY> L;
     const uint32_t t = xcd_order(blockIdx.x, (uint32_t)(ntx * nty * ntz));
     const int tx = t % ntx, ty_ = (t / ntx) % nty, tz = t / (ntx * nty);
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    tile_step<T, DIAG, TY>(g, in, out, mom, c, tx * 64, ty_ * TY, tz * TZ, TZ, L, acc);
+    tile_step<T, DIAG, TY, NT>(g, in, out, mom, c, tx * 64, ty_ * TY, tz * TZ, TZ, L, acc, alpha, plane);
     if constexpr (DIAG) block_sum_store<6, TY + 3>(acc, part, SL_EPS, t);
 }
 
 // Ensemble of boxes in one launch: the blocks of box k are [blk0[k], blk0[k+1])
 // of the XCD-ordered grid; each box has its own fields, coefficients and
 // partials (indexed by the box-local block).
-template <typename T, bool DIAG, int TY>
+template <typename T, bool DIAG, int TY, bool NT>
 __global__ __launch_bounds__(64 * (TY + 3)) void step_tile_batch_kernel(const BatchBox<T> *boxes, int nbox,
                                                                         int parity, const StepCoef<T> *coef,
                                                                         uint32_t nblk) {
@@ -309,8 +316,8 @@ __global__ __launch_bounds__(64 * (TY + 3)) void step_tile_batch_kernel(const Ba
     const uint32_t lt = t - bx.blk0;
     const int tx = lt % bx.ntx, ty_ = (lt / bx.ntx) % bx.nty, tz = lt / (bx.ntx * bx.nty);
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    tile_step<T, DIAG, TY>(bx.g, bx.f[parity], bx.f[1 - parity], bx.mom, coef[lo], tx * 64, ty_ * TY, tz * bx.tz,
-                           bx.tz, L, acc);
+    tile_step<T, DIAG, TY, NT>(bx.g, bx.f[parity], bx.f[1 - parity], bx.mom, coef[lo], tx * 64, ty_ * TY, tz * bx.tz,
+                           bx.tz, L, acc, bx.alpha, bx.plane);
     if constexpr (DIAG) block_sum_store<6, TY + 3>(acc, bx.part, SL_EPS, lt);
 }
 
@@ -323,41 +330,51 @@ uint32_t tile_blocks(const Geom &g, TileShape ts) {
 
 template <typename T, int TY>
 static hipError_t launch_ty(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, const StepCoef<T> &c, bool diag,
-                            Partials part, int tz, hipStream_t st) {
+                            Partials part, int tz, T *alpha, uint32_t plane, bool nt, hipStream_t st) {
     const int ntx = (g.nx + 63) / 64, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + tz - 1) / tz;
     dim3 block(64, TY + 3, 1);
     dim3 grid((unsigned)(ntx * nty * ntz), 1, 1);
-    if (diag)
-        step_tile_kernel<T, true, TY><<<grid, block, 0, st>>>(g, in, out, mom, c, part, tz, ntx, nty, ntz);
-    else
-        step_tile_kernel<T, false, TY><<<grid, block, 0, st>>>(g, in, out, mom, c, part, tz, ntx, nty, ntz);
+#define MTS_TILE_LAUNCH(D, N) \
+    step_tile_kernel<T, D, TY, N><<<grid, block, 0, st>>>(g, in, out, mom, c, part, tz, ntx, nty, ntz, alpha, plane)
+    if (diag) {
+        if (nt) MTS_TILE_LAUNCH(true, true);
+        else MTS_TILE_LAUNCH(true, false);
+    } else {
+        if (nt) MTS_TILE_LAUNCH(false, true);
+        else MTS_TILE_LAUNCH(false, false);
+    }
+#undef MTS_TILE_LAUNCH
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, const StepCoef<T> &c, bool diag,
-                            Partials part, TileShape ts, hipStream_t st) {
+                            Partials part, TileShape ts, T *alpha, uint32_t plane, bool nt, hipStream_t st) {
     switch (ts.ty) {
-        case 4: return launch_ty<T, 4>(g, in, out, mom, c, diag, part, ts.tz, st);
-        case 8: return launch_ty<T, 8>(g, in, out, mom, c, diag, part, ts.tz, st);
-        case 12: return launch_ty<T, 12>(g, in, out, mom, c, diag, part, ts.tz, st);
+        case 4: return launch_ty<T, 4>(g, in, out, mom, c, diag, part, ts.tz, alpha, plane, nt, st);
+        case 8: return launch_ty<T, 8>(g, in, out, mom, c, diag, part, ts.tz, alpha, plane, nt, st);
+        case 12: return launch_ty<T, 12>(g, in, out, mom, c, diag, part, ts.tz, alpha, plane, nt, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T>
 hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32_t nblk, int parity,
-                                  const StepCoef<T> *coef_dev, bool diag, int ty, hipStream_t st) {
+                                  const StepCoef<T> *coef_dev, bool diag, int ty, bool nt, hipStream_t st) {
     dim3 grid(nblk, 1, 1);
-#define MTS_BATCH_CASE(TYV)                                                                                  \
-    case TYV: {                                                                                              \
-        dim3 block(64, TYV + 3, 1);                                                                          \
-        if (diag)                                                                                            \
-            step_tile_batch_kernel<T, true, TYV><<<grid, block, 0, st>>>(boxes_dev, nbox, parity, coef_dev, nblk); \
-        else                                                                                                 \
-            step_tile_batch_kernel<T, false, TYV><<<grid, block, 0, st>>>(boxes_dev, nbox, parity, coef_dev, nblk); \
-        return hipGetLastError();                                                                            \
-    }
+#define MTS_BATCH_LAUNCH(TYV, D, N)                                                                                 \
+    step_tile_batch_kernel<T, D, TYV, N><<<grid, dim3(64, TYV + 3, 1), 0, st>>>(boxes_dev, nbox, parity, coef_dev, \
+                                                                                 nblk)
+#define MTS_BATCH_CASE(TYV)                                           \
+    case TYV:                                                         \
+        if (diag) {                                                   \
+            if (nt) MTS_BATCH_LAUNCH(TYV, true, true);                \
+            else MTS_BATCH_LAUNCH(TYV, true, false);                  \
+        } else {                                                      \
+            if (nt) MTS_BATCH_LAUNCH(TYV, false, true);               \
+            else MTS_BATCH_LAUNCH(TYV, false, false);                 \
+        }                                                             \
+        return hipGetLastError();
     switch (ty) {
         MTS_BATCH_CASE(4)
         MTS_BATCH_CASE(8)
@@ -365,16 +382,19 @@ hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32
         default: return hipErrorInvalidValue;
     }
 #undef MTS_BATCH_CASE
+#undef MTS_BATCH_LAUNCH
 }
 
 template hipError_t launch_step_tile_batch<float>(const BatchBox<float> *, int, uint32_t, int, const StepCoef<float> *,
-                                                  bool, int, hipStream_t);
+                                                  bool, int, bool, hipStream_t);
 template hipError_t launch_step_tile_batch<double>(const BatchBox<double> *, int, uint32_t, int,
-                                                   const StepCoef<double> *, bool, int, hipStream_t);
+                                                   const StepCoef<double> *, bool, int, bool, hipStream_t);
 
 template hipError_t launch_step_tile<float>(const Geom &, Fields<float>, Fields<float>, Moms<float>,
-                                            const StepCoef<float> &, bool, Partials, TileShape, hipStream_t);
+                                            const StepCoef<float> &, bool, Partials, TileShape, float *, uint32_t,
+                                            bool, hipStream_t);
 template hipError_t launch_step_tile<double>(const Geom &, Fields<double>, Fields<double>, Moms<double>,
-                                             const StepCoef<double> &, bool, Partials, TileShape, hipStream_t);
+                                             const StepCoef<double> &, bool, Partials, TileShape, double *, uint32_t,
+                                             bool, hipStream_t);
 
 }  // namespace mts

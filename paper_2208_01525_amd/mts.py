@@ -18,11 +18,11 @@ MTS_OK, MTS_EINVAL, MTS_EUNSTABLE, MTS_ENOMEM, MTS_EHIP, MTS_ENONFINITE = 0, -1,
 MTS_FP32, MTS_FP64 = 1, 2
 
 EXPORTS = ("mts_state_bytes", "mts_create", "mts_destroy", "mts_init_fields", "mts_step", "mts_cool", "mts_diagnostics",
-           "mts_get_fields", "mts_set_fields", "mts_get_windings", "mts_get_cells", "mts_get_sites", "mts_segments", "mts_set_tile", "mts_get_tile", "mts_autotune", "mts_timing_enable",
+           "mts_get_fields", "mts_set_fields", "mts_get_windings", "mts_get_cells", "mts_get_sites", "mts_segments", "mts_set_tile", "mts_get_tile", "mts_set_streaming_stores", "mts_get_streaming_stores", "mts_autotune", "mts_timing_enable",
            "mts_timing_read", "mts_last_error", "mts_strerror",
            "mts_batch_state_bytes", "mts_batch_create", "mts_batch_destroy", "mts_batch_size",
            "mts_batch_init_fields", "mts_batch_step", "mts_batch_diagnostics", "mts_batch_get_fields",
-           "mts_batch_set_fields", "mts_batch_set_tile", "mts_batch_timing_read", "mts_batch_autotune",
+           "mts_batch_set_fields", "mts_batch_set_tile", "mts_batch_set_streaming_stores", "mts_batch_get_streaming_stores", "mts_batch_timing_read", "mts_batch_autotune",
            "mts_batch_last_error")
 
 
@@ -106,6 +106,10 @@ def load():
                                ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     L.mts_get_sites.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
     L.mts_set_tile.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.mts_set_streaming_stores.argtypes = [vp, ctypes.c_int32]
+    L.mts_batch_set_streaming_stores.argtypes = [vp, ctypes.c_int32]
+    L.mts_get_streaming_stores.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.mts_batch_get_streaming_stores.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.mts_get_tile.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     i32p = ctypes.POINTER(ctypes.c_int32)
     L.mts_autotune.argtypes = [vp, ctypes.c_int32, i32p, i32p, ctypes.POINTER(ctypes.c_double)]
@@ -264,6 +268,14 @@ class Lattice:
     def set_tile(self, ty, tz):
         self._check(self.L.mts_set_tile(self.ctx, int(ty), int(tz)))
 
+    def set_streaming_stores(self, on):
+        self._check(self.L.mts_set_streaming_stores(self.ctx, 1 if on else 0))
+
+    def get_streaming_stores(self):
+        v = ctypes.c_int32()
+        self._check(self.L.mts_get_streaming_stores(self.ctx, ctypes.byref(v)))
+        return bool(v.value)
+
     def get_tile(self):
         ty, tz = ctypes.c_int32(), ctypes.c_int32()
         self._check(self.L.mts_get_tile(self.ctx, ctypes.byref(ty), ctypes.byref(tz)))
@@ -367,6 +379,14 @@ class Batch:
         self._check(self.L.mts_batch_autotune(self.b, int(steps), ctypes.byref(ty), ctypes.byref(tz),
                                               ctypes.byref(ms)))
         return ty.value, tz.value, ms.value
+
+    def set_streaming_stores(self, on):
+        self._check(self.L.mts_batch_set_streaming_stores(self.b, 1 if on else 0))
+
+    def get_streaming_stores(self):
+        v = ctypes.c_int32()
+        self._check(self.L.mts_batch_get_streaming_stores(self.b, ctypes.byref(v)))
+        return bool(v.value)
 
     def timing_read(self):
         st, ms = ctypes.c_int64(), ctypes.c_double()

@@ -561,6 +561,77 @@ def test_velocity_estimator_on_exact_plane_waves():
         assert d["v2_pq"] == pytest.approx(2 * R / (1 + R), rel=1e-9)
 
 
+# --------------------------------------------------------------- P13 static string, P17 stability
+
+
+def _relaxed_string_pair(scale):
+    """A straight vortex / antivortex pair along z, 8 length units apart in a periodic box,
+    relaxed by the gradient flow for 50 time units (kappa = 0, psi in its vacuum,
+    lambda = 2 e^2: critical coupling).  The energy is then converged to ~1e-5 relative; the
+    pair's residual attraction only moves it at the 1e-6 level."""
+    h = 0.5 / scale
+    nx, ny, nz = 32 * scale, 16 * scale, 2
+    m = O.model(nx, ny, nz, h=h, k=0.1 / scale, kappa=0.0)
+    st = I.string_pairs(nx, ny, nz, p_pair=(8 * scale - 1, 24 * scale - 1, 8 * scale - 1), core=2.0 * scale)
+    O.cool(m, st, 1500 * scale ** 2, (1.0 / 30.0) / scale ** 2)
+    return m, st, O.hamiltonian(m, st) / (2.0 * nz * h)
+
+
+def test_static_string_tension_is_2_pi_sigma_squared():
+    """P13: at critical coupling (lambda = 2 e^2, as in Sec. IV) a static string has
+    tension 2 pi sigma^2.  The relaxed lattice pair's energy per unit length per string
+    approaches it as O(h^2): the deficit shrinks about 4x when h halves.  A wrong factor in
+    any term of the energy (gradient, magnetic, potential) moves it off the BPS value."""
+    _, _, mu_coarse = _relaxed_string_pair(1)
+    _, _, mu_fine = _relaxed_string_pair(2)
+    d_coarse = 1.0 - mu_coarse / (2.0 * math.pi)
+    d_fine = 1.0 - mu_fine / (2.0 * math.pi)
+    assert 0.005 < d_coarse < 0.02, mu_coarse
+    assert 0.0 < d_fine < 0.005, mu_fine
+    assert 3.5 < d_coarse / d_fine < 4.7, (d_coarse, d_fine)
+
+
+def test_static_string_stays_put_without_expansion():
+    """P13: the relaxed pair is a static solution of the update at m = 0: over 10 time
+    units the windings stay on the same plaquettes, the momenta grow no faster than the
+    residual force of the relaxed state allows (|pi| <= 2 |F| t; a wrong term in the update
+    would make the relaxed state far from a fixed point) and the energy is unchanged."""
+    m, st, _ = _relaxed_string_pair(1)
+    f0 = np.abs(O.forces(m, st)).max()
+    assert f0 < 1e-3
+    W0 = O.windings(m, st)
+    e0 = O.hamiltonian(m, st)
+    O.run(m, st, 100, 1.0, 0.0, 1.0)
+    t = 100 * m.k
+    assert np.array_equal(O.windings(m, st), W0)
+    assert np.abs(st[I.PI:I.PI + 4]).max() < 2.0 * f0 * t
+    assert np.abs(st[I.E:I.E + 6]).max() < 2.0 * f0 * t
+    assert O.hamiltonian(m, st) == pytest.approx(e0, rel=1e-6)
+
+
+@pytest.mark.parametrize("factor,stable", [(0.97, True), (1.03, False)])
+def test_leapfrog_stability_threshold(factor, stable):
+    """P17: the vacuum is stable while k^2 (12/h^2 + a^{2s} mu2_max) < 4, with mu2_max =
+    lambda + 2 kappa the heavier eigenvalue of the vacuum mass matrix of Sec. II, and blows
+    up just above it (the staggered mode of the heavier scalar combination)."""
+    nx = 8
+    m = O.model(nx)
+    mu2 = 2.0 + 2.0 * 0.9
+    a2s = factor * (4.0 / m.k ** 2 - 12.0 / m.h ** 2) / mu2
+    st = I.empty(nx, nx, nx)
+    st[I.PHI] = 1.0
+    st[I.PSI] = 1.0
+    st += np.random.default_rng(5).normal(0.0, 1e-6, size=st.shape)
+    with np.errstate(all="ignore"):
+        for j in range(200):
+            O.step_coeffs(m, st, 10.0 + j * m.k, math.sqrt(a2s), 0.0, 0.0, 1.0)
+        dev = np.abs(st[[I.PHI, I.PSI]] - 1.0).max()
+    if stable:
+        assert dev < 1e-4
+    else:
+        assert not np.isfinite(dev) or dev > 1.0
+
+
 # --------------------------------------------------------------- diffusive cooling (Sec. III)
 
 

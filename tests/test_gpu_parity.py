@@ -351,7 +351,8 @@ def _patch_sites(shape, centre, r=2):
 
 
 def test_full_size_workload_sampled():
-    """The benchmarked configuration at its full size: 512^3, FP32, default tile, diagnostics
+    """The benchmarked configuration at its full size and launch configuration: 512^3, FP32,
+    the tile shape and store mode the autotuner picks (as the benchmark does), diagnostics
     every 10 steps, radiation era with s = 1, seeded random phases.  After 10 steps, the 11th
     (a diagnostic step) is checked at sampled sites -- tile corners and edges in x, y and z,
     the box faces and random sites -- against the oracle's step on a 5^3 patch around each
@@ -359,7 +360,8 @@ def test_full_size_workload_sampled():
     The Gauss law and finiteness are checked over the whole box through the record."""
     n = 512
     lat = lattice(n, n, n, "fp32", eta_ref=128.0, diag_every=10)
-    assert lat.get_tile() == (8, 32)
+    assert lat.get_tile() == (8, 32) and lat.get_streaming_stores()
+    lat.autotune(4)
     lat.init_fields(1)
     lat.step(10, 1.0, 0.5, 1.0)
     rng = np.random.default_rng(7)
@@ -494,6 +496,41 @@ def test_1024_workload_sampled(precision):
         assert err <= 64 * U[precision] * max(1.0, np.abs(st[:, 2, 2, 2]).max()), (c, err)
     recs = lat.diagnostics()
     assert len(recs) == 1 and recs[0]["flags"] == 0
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+
+
+def test_1280_workload_sampled():
+    """1280^3 FP32 (252 GB of state: the largest cube one MI355X holds), radiation era, s = 1,
+    diagnostics every 50 steps: 50 steps from eta = 1, then a diagnostic step checked at
+    sampled sites against the oracle's step on 5^3 patches, and the whole-box record."""
+    n = 1280
+    torch.cuda.empty_cache()
+    need = P.state_bytes(P.make_params(n, eta_ref=201.0)) * 1.12
+    if torch.cuda.mem_get_info()[0] < need:
+        pytest.skip(f"needs {need / 1e9:.0f} GB free on the device")
+    lat = lattice(n, n, n, "fp32", eta_ref=201.0, diag_every=50)
+    lat.init_fields(1)
+    lat.step(50, 1.0, 0.5, 1.0)
+    rng = np.random.default_rng(11)
+    samples = [(0, 0, 0), (1279, 1279, 1279), (31, 7, 63), (32, 8, 64), (640, 1272, 1279), (1279, 0, 640)]
+    samples += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(14)]
+    patches = [_patch_sites((n, n, n), c) for c in samples]
+    before = lat.get_sites(np.concatenate(patches))
+    lat.step(1, 6.0, 0.5, 1.0)
+    after = lat.get_sites(np.array([p[62] for p in patches], dtype=np.uint64))
+    m = O.model(5, eta_ref=201.0)
+    for k, c in enumerate(samples):
+        st = np.ascontiguousarray(before[125 * k:125 * (k + 1)].T.reshape(20, 5, 5, 5))
+        O.step(m, st, 6.0, 0.5, 1.0)
+        err = np.abs(st[:, 2, 2, 2] - after[k]).max()
+        assert err <= 64 * U["fp32"] * max(1.0, np.abs(st[:, 2, 2, 2]).max()), (c, err)
+    recs = lat.diagnostics()
+    assert len(recs) == 2 and recs[-1]["step"] == 50 and recs[-1]["flags"] == 0
+    r = recs[-1]
+    assert all(np.isfinite([r["sum_energy"], r["sum_lagrangian"], r["sum_KL"], r["sum_GL"]]))
+    assert max(r["gauss_rel"]) < 2e-5
     lat.close()
     del lat
     torch.cuda.empty_cache()

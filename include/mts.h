@@ -99,8 +99,9 @@ typedef struct mts_diag {
 typedef struct mts_ctx mts_ctx;
 
 /* Bytes of the device state buffer a context needs: 30 planes of
- * nx*ny*nz (rounded up to 64) elements of the precision's type -- the 20
- * live components plus a second copy of the 10 field components (the
+ * nx*ny*nz (rounded up to 64) elements of the precision's type plus 4096
+ * bytes each (a stagger of the plane base addresses across HBM channels) --
+ * the 20 live components plus a second copy of the 10 field components (the
  * drift writes the new fields into the other copy). */
 size_t mts_state_bytes(const mts_params *p);
 
@@ -222,9 +223,8 @@ int mts_set_tile(mts_ctx *ctx, int32_t ty, int32_t tz);
 int mts_get_tile(const mts_ctx *ctx, int32_t *ty, int32_t *tz);
 
 /* Streaming (non-temporal) stores for the tiled update's outputs: on (1,
- * the default of a single box) or off (0, the default of a batch).  Which
- * is faster depends on the launch; results are bitwise identical.  The
- * autotuners try both. */
+ * the default) or off (0).  Which is faster depends on the launch and the
+ * box sizes; results are bitwise identical.  The autotuners try both. */
 int mts_set_streaming_stores(mts_ctx *ctx, int32_t on);
 int mts_get_streaming_stores(const mts_ctx *ctx, int32_t *on);
 

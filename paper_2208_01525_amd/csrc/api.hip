@@ -29,7 +29,7 @@ struct mts_ctx {
     size_t esz = 4;
     Geom g{};
     uint64_t S = 0;              // sites
-    uint64_t plane = 0;          // elements per plane (S rounded up to 64)
+    uint64_t plane = 0;          // elements per plane (S rounded up to 64, plus the stagger)
     char *state = nullptr;
     hipStream_t stream = nullptr;
     int cur = 0;                 // which field copy holds the current fields
@@ -177,9 +177,18 @@ int check_params(const mts_params *p, std::string &why) {
     return MTS_OK;
 }
 
+// Consecutive planes are staggered by an extra 4 KiB so that the 30 plane base
+// addresses of a box whose plane size is a power of two do not all fall on
+// the same HBM channel offset (measured: +2-7 % on the update's access
+// pattern).
+#ifndef MTS_PLANE_PAD_BYTES
+#define MTS_PLANE_PAD_BYTES 4096
+#endif
+
 uint64_t plane_of(const mts_params &p) {
     const uint64_t S = (uint64_t)p.nx * p.ny * p.nz;
-    return (S + 63) / 64 * 64;
+    const uint64_t esz = p.precision == MTS_FP64 ? 8 : 4;
+    return (S + 63) / 64 * 64 + MTS_PLANE_PAD_BYTES / esz;
 }
 
 hipEvent_t next_event(mts_ctx *c) {
@@ -831,7 +840,7 @@ struct mts_batch {
     void *boxes_diag_dev = nullptr;  // BatchBox<T>[nbox] for diagnostic steps (their own tile rows)
     int32_t ty_diag = 8;
     uint32_t nblk_diag = 0;
-    bool nt = false;                 // plain stores: measured faster for ensembles of small boxes
+    bool nt = true;                  // streaming stores in the tiled update
     void *coef_dev = nullptr;        // StepCoef<T>[n][nbox]
     size_t coef_cap = 0;             // bytes
     int32_t ty = 8;

@@ -50,9 +50,19 @@ struct Pi<double> {
 
 // Stores of data written once per step and not re-read by this launch.
 // With NT they are streaming (non-temporal) stores that bypass L2
-// allocation, leaving L2 to the halo rows neighbouring tiles share; which
-// mode is faster depends on the launch (measured: streaming helps a single
-// large box, plain stores an ensemble of small ones), so it is tunable.
+// allocation, leaving L2 to the halo rows neighbouring tiles share; the
+// gain depends on the launch (measured 1-3 %), so it is tunable.
+// A pointer known to address global memory.  Pointers read from a table in
+// device memory are generic to the compiler, which then emits FLAT accesses
+// (counted against the LDS wait counter as well, so every LDS wait also
+// drains outstanding HBM loads); the round trip through the global address
+// space lets it emit global loads and stores instead.
+template <typename P>
+__device__ __forceinline__ P *as_global(P *p) {
+    auto *g = (__attribute__((address_space(1))) P *)(uintptr_t)p;
+    return (P *)g;
+}
+
 template <bool NT, typename T>
 __device__ __forceinline__ void st_stream(T *p, T v) {
     if constexpr (NT)

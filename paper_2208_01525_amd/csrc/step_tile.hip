@@ -315,10 +315,29 @@ __global__ __launch_bounds__(64 * (TY + 3)) void step_tile_batch_kernel(const Ba
     const BatchBox<T> &bx = boxes[lo];
     const uint32_t lt = t - bx.blk0;
     const int tx = lt % bx.ntx, ty_ = (lt / bx.ntx) % bx.nty, tz = lt / (bx.ntx * bx.nty);
+    // the box table's pointers all address global memory
+    Fields<T> fin, fout;
+    Moms<T> mom;
+#pragma unroll
+    for (int sec = 0; sec < 2; sec++) {
+        fin.phi[sec] = as_global(bx.f[parity].phi[sec]);
+        fout.phi[sec] = as_global(bx.f[1 - parity].phi[sec]);
+        mom.pi[sec] = as_global(bx.mom.pi[sec]);
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            fin.A[sec][i] = as_global(bx.f[parity].A[sec][i]);
+            fout.A[sec][i] = as_global(bx.f[1 - parity].A[sec][i]);
+            mom.E[sec][i] = as_global(bx.mom.E[sec][i]);
+        }
+    }
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    tile_step<T, DIAG, TY, NT>(bx.g, bx.f[parity], bx.f[1 - parity], bx.mom, coef[lo], tx * 64, ty_ * TY, tz * bx.tz,
-                           bx.tz, L, acc, bx.alpha, bx.plane);
-    if constexpr (DIAG) block_sum_store<6, TY + 3>(acc, bx.part, SL_EPS, lt);
+    tile_step<T, DIAG, TY, NT>(bx.g, fin, fout, mom, coef[lo], tx * 64, ty_ * TY, tz * bx.tz, bx.tz, L, acc,
+                               as_global(bx.alpha), bx.plane);
+    if constexpr (DIAG) {
+        Partials part = bx.part;
+        part.base = as_global(part.base);
+        block_sum_store<6, TY + 3>(acc, part, SL_EPS, lt);
+    }
 }
 
 bool tile_supported(TileShape ts) { return (ts.ty == 4 || ts.ty == 8 || ts.ty == 12) && ts.tz >= 1; }

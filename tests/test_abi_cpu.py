@@ -66,12 +66,14 @@ def test_struct_layout_matches_header():
 
 
 def test_state_bytes():
+    """30 planes of the site count rounded up to 64 elements, each followed by a 4 KiB
+    stagger."""
     p = P.make_params(64, eta_ref=17.0)
-    assert P.state_bytes(p) == 30 * 64 ** 3 * 4
+    assert P.state_bytes(p) == 30 * (64 ** 3 * 4 + 4096)
     p = P.make_params(5, 6, 7, precision="fp64")
-    assert P.state_bytes(p) == 30 * 256 * 8          # 210 sites rounded up to 256
+    assert P.state_bytes(p) == 30 * (256 * 8 + 4096)          # 210 sites rounded up to 256
     p512 = P.make_params(512, eta_ref=128.0)
-    assert P.state_bytes(p512) == 30 * 512 ** 3 * 4  # 16.1 GB: fits one MI355X
+    assert P.state_bytes(p512) == 30 * (512 ** 3 * 4 + 4096)  # 16.1 GB: fits one MI355X
 
 
 @pytest.mark.parametrize("field,value", [

@@ -190,33 +190,46 @@ bool overlap_uses_bits(const Geom &g) { return g.nx % 64 == 0; }
 uint32_t overlap_words(const Geom &g) { return (uint32_t)(g.nx / 64) * (uint32_t)g.ny * (uint32_t)g.nz; }
 
 // Cell value = sum of |W| over the six faces of the cell [x, x+1]^3; with
-// `bits`, also the 64-cell occupancy words of each sector.
+// `bits`, also the 64-cell occupancy words of each sector.  A block holds
+// 64 x 4 columns and walks CZ planes, carrying the packed |W| byte of the
+// next plane (the upper z face) over to the following iteration.
+constexpr int CZ = 16;
+
 __global__ __launch_bounds__(256) void cells_kernel(Geom g, const uint8_t *wabs, uint8_t *cells, uint64_t *bits,
                                                     uint32_t plane, uint32_t nwords) {
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y = blockIdx.y * 4 + threadIdx.y;
-    const int z = blockIdx.z;
     const bool in = x < g.nx && y < g.ny;
-    uint32_t n[2] = {0, 0};
+    const int z0 = blockIdx.z * CZ, z1 = min(z0 + CZ, g.nz);
+    const uint32_t col = in ? (uint32_t)x + (uint32_t)g.nx * (uint32_t)y : 0u;
+    const uint32_t colx = in ? (uint32_t)wrap1(x + 1, g.nx) + (uint32_t)g.nx * (uint32_t)y : 0u;
+    const uint32_t coly = in ? (uint32_t)x + (uint32_t)g.nx * (uint32_t)wrap1(y + 1, g.ny) : 0u;
+    uint32_t w0[2] = {0, 0};
     if (in) {
-        const uint32_t s = x + g.nx * y + g.nxy * z;
-        const uint32_t sx = wrap1(x + 1, g.nx) + g.nx * y + g.nxy * z;
-        const uint32_t sy = x + g.nx * wrap1(y + 1, g.ny) + g.nxy * z;
-        const uint32_t sz = x + g.nx * y + g.nxy * wrap1(z + 1, g.nz);
 #pragma unroll
-        for (int sec = 0; sec < 2; sec++) {
-            const uint8_t *w = wabs + (size_t)sec * plane;
-            const uint32_t w0 = w[s];
-            n[sec] = (w0 & 3) + (w[sx] & 3) + ((w0 >> 2) & 3) + ((w[sy] >> 2) & 3) + ((w0 >> 4) & 3) + ((w[sz] >> 4) & 3);
-            cells[(size_t)sec * plane + s] = (uint8_t)n[sec];
-        }
+        for (int sec = 0; sec < 2; sec++) w0[sec] = wabs[(size_t)sec * plane + col + g.nxy * (uint32_t)z0];
     }
-    if (bits) {   // nx % 64 == 0: the wave is one 64-cell word of one row
-        const uint64_t mp = __ballot(in && n[0] > 0), mq = __ballot(in && n[1] > 0);
-        if (threadIdx.x == 0 && in) {
-            const uint32_t wi = (uint32_t)(x / 64) + (uint32_t)(g.nx / 64) * ((uint32_t)y + (uint32_t)g.ny * z);
-            bits[wi] = mp;
-            bits[(size_t)nwords + wi] = mq;
+    for (int z = z0; z < z1; z++) {
+        uint32_t n[2] = {0, 0};
+        if (in) {
+            const uint32_t off = g.nxy * (uint32_t)z, offz = g.nxy * (uint32_t)wrap1(z + 1, g.nz);
+#pragma unroll
+            for (int sec = 0; sec < 2; sec++) {
+                const uint8_t *w = wabs + (size_t)sec * plane;
+                const uint32_t wz = w[col + offz];
+                n[sec] = (w0[sec] & 3) + (w[colx + off] & 3) + ((w0[sec] >> 2) & 3) + ((w[coly + off] >> 2) & 3) +
+                         ((w0[sec] >> 4) & 3) + ((wz >> 4) & 3);
+                cells[(size_t)sec * plane + col + off] = (uint8_t)n[sec];
+                w0[sec] = wz;
+            }
+        }
+        if (bits) {   // nx % 64 == 0: the wave is one 64-cell word of one row
+            const uint64_t mp = __ballot(in && n[0] > 0), mq = __ballot(in && n[1] > 0);
+            if (threadIdx.x == 0 && in) {
+                const uint32_t wi = (uint32_t)(x / 64) + (uint32_t)(g.nx / 64) * ((uint32_t)y + (uint32_t)g.ny * z);
+                bits[wi] = mp;
+                bits[(size_t)nwords + wi] = mq;
+            }
         }
     }
 }
@@ -224,7 +237,7 @@ __global__ __launch_bounds__(256) void cells_kernel(Geom g, const uint8_t *wabs,
 hipError_t launch_cells(const Geom &g, const uint8_t *wabs, uint8_t *cells, uint64_t *bits, uint32_t plane,
                         hipStream_t st) {
     dim3 block(64, 4, 1);
-    dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+    dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, (g.nz + CZ - 1) / CZ);
     cells_kernel<<<grid, block, 0, st>>>(g, wabs, cells, overlap_uses_bits(g) ? bits : nullptr, plane,
                                          overlap_words(g));
     return hipGetLastError();

@@ -45,12 +45,16 @@ def measured_traffic(n, precision, tile, nt):
     mode and workload; else None."""
     if n != 512 or precision != "fp32" or not os.path.exists(TRAFFIC_FILE):
         return None
-    kv = dict(l.strip().split("=", 1) for l in open(TRAFFIC_FILE) if "=" in l and not l.startswith("#"))
-    if kv.get("source_sha256") != kernel_source_hash() or kv.get("tile") != f"{tile[0]},{tile[1]}":
+    lines = [l.strip() for l in open(TRAFFIC_FILE) if l.strip() and not l.startswith("#")]
+    head = dict(l.split("=", 1) for l in lines if " " not in l and "=" in l)
+    if head.get("source_sha256") != kernel_source_hash():
         return None
-    if kv.get("streaming_stores") != str(int(nt)):
-        return None
-    return int(kv["bytes_per_launch"])
+    want = f"{tile[0]},{tile[1]},{int(nt)}"
+    for l in lines:
+        kv = dict(f.split("=", 1) for f in l.split() if "=" in f)
+        if kv.get("config") == want:
+            return int(kv["bytes_per_launch"])
+    return None
 
 
 def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0.5, s=1.0, eta_ref=128.0, seed=1,

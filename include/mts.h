@@ -56,7 +56,7 @@ extern "C" {
 
 /* ----------------------------------------------------------- params */
 typedef struct mts_params {
-    int32_t nx, ny, nz;      /* box, each >= 4; nx*ny*nz < 2^32                 */
+    int32_t nx, ny, nz;      /* box, each >= 4; nx*ny*nz < 2^32 - 2048          */
     int32_t precision;       /* MTS_FP32 or MTS_FP64                            */
     double dx;               /* lattice spacing h > 0        (paper: 0.5)       */
     double dt;               /* conformal time step k > 0    (paper: 0.1)       */

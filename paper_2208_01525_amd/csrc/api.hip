@@ -164,7 +164,8 @@ int check_params(const mts_params *p, std::string &why) {
     if (!p) return why = "params is NULL", MTS_EINVAL;
     if (p->nx < 4 || p->ny < 4 || p->nz < 4) return why = "each of nx, ny, nz must be >= 4", MTS_EINVAL;
     const double S = (double)p->nx * p->ny * p->nz;
-    if (S >= 4294967296.0 - 64) return why = "nx*ny*nz must be below 2^32", MTS_EINVAL;
+    // planes (S rounded up to 64 plus the stagger) are indexed with 32 bits
+    if (S >= 4294967296.0 - 2048) return why = "nx*ny*nz must be below 2^32 - 2048", MTS_EINVAL;
     if (p->precision != MTS_FP32 && p->precision != MTS_FP64) return why = "precision must be MTS_FP32 or MTS_FP64", MTS_EINVAL;
     if (!(p->dx > 0) || !(p->dt > 0)) return why = "dx and dt must be > 0", MTS_EINVAL;
     if (!(p->e_p > 0) || !(p->e_q > 0)) return why = "e_p and e_q must be > 0", MTS_EINVAL;

@@ -90,8 +90,14 @@ def test_invalid_params_rejected_without_gpu(field, value):
 
 
 def test_too_large_box_rejected():
+    """Planes are indexed with 32 bits: the site count plus the plane stagger must fit."""
     p = P.make_params(2048, 2048, 1024, eta_ref=4.0)     # 2^32 sites
     assert P.state_bytes(p) == 0
+    p = P.make_params(4, 4, 268435392, eta_ref=4.0)      # 2^32 - 1024 sites: the stagger would overflow
+    assert 4 * 4 * 268435392 == 2 ** 32 - 1024
+    assert P.state_bytes(p) == 0
+    p = P.make_params(2048, 2048, 1023, eta_ref=4.0)     # just below: accepted
+    assert P.state_bytes(p) == 30 * ((2048 * 2048 * 1023) * 4 + 4096)
 
 
 def test_create_checks_buffer_before_gpu():

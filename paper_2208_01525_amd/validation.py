@@ -51,7 +51,8 @@ def asymptotic(records, eta_lo, eta_hi):
 
 def run(n, era_m, seed, m_damp=0.9, dx=0.5, dt=0.1, diag_every=10, eta_lo=230.0, eta_end=None,
         device="cuda:0", chunk=200, log=sys.stderr):
-    """One validation run; returns (records, asymptotic values)."""
+    """One validation run; returns (records, asymptotic values).  Progress lines go to
+    `log` (None: silent)."""
     eta_end = eta_end if eta_end is not None else n * dx / 2.0
     params = M.make_params(n, eta_ref=eta_end, diag_every=diag_every, dx=dx, dt=dt)
     lat = M.Lattice(params, device=device)
@@ -71,9 +72,10 @@ def run(n, era_m, seed, m_damp=0.9, dx=0.5, dt=0.1, diag_every=10, eta_lo=230.0,
             done += c
             records += lat.diagnostics()
             r = records[-1] if records else None
-            print(f"seed {seed} m {era_m:.3f}: eta {5.0 + done * dt:.1f}, "
-                  f"xi_W {r['xi_W'] if r else float('nan'):.2f}, {time.perf_counter() - t0:.0f} s",
-                  file=log, flush=True)
+            if log is not None:
+                print(f"seed {seed} m {era_m:.3f}: eta {5.0 + done * dt:.1f}, "
+                      f"xi_W {r['xi_W'] if r else float('nan'):.2f}, {time.perf_counter() - t0:.0f} s",
+                      file=log, flush=True)
     finally:
         lat.close()
     return records, asymptotic(records, eta_lo, eta_end)

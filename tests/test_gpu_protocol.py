@@ -27,3 +27,20 @@ def test_protocol_forms_a_coarsening_network(physical):
     assert late[-1]["xi_W"] > late[0]["xi_W"]
     # and it is still a network of both species
     assert late[-1]["wind_abs"][0] > 0 and late[-1]["wind_abs"][1] > 0
+
+
+def test_validation_driver_small_box():
+    """The Sec. IV validation driver on a 64^3 box (eta 1 -> 16): constant comoving width
+    conserves Gauss's law to FP32 rounding, the estimators of the window are finite and in
+    range, and the network is still made of both species."""
+    from paper_2208_01525_amd import validation
+
+    records, asym = validation.run(64, 0.5, seed=4, eta_lo=12.0, chunk=50, log=None)
+    # records every 10 steps from the damped phase on (eta = 1, 2, ...) up to eta = 15
+    assert records[0]["eta"] == pytest.approx(1.0) and records[-1]["eta"] == pytest.approx(15.0)
+    assert len(records) == 15
+    assert asym["records"] == 4
+    assert asym["gauss_rel_max"] < 1e-4
+    assert 0.0 < asym["v2_lag"] < 1.0
+    assert asym["xi_W_end"] > 0 and math.isfinite(asym["xi_W_dot"])
+    assert records[-1]["wind_abs"][0] > 0 and records[-1]["wind_abs"][1] > 0

@@ -545,14 +545,19 @@ int mts_cool(mts_ctx *c, int32_t n, double dt_cool) {
     q.kappa = 0.0;             // the printed cooling equations have no coupling term
     q.dt = dt_cool;
     const Book b{1.0, 0.0, 0.0, 1.0};
+    const bool tiled = c->tile.ty != 0;
     for (int32_t j = 0; j < n; j++) {
         hipError_t e;
         if (c->p.precision == MTS_FP64)
-            e = launch_cool<double>(c->g, fields_of<double>(c, c->cur), fields_of<double>(c, 1 - c->cur),
-                                    moms_of<double>(c), coefficients<double>(q, b, 1.0), c->stream);
+            e = tiled ? launch_cool_tile<double>(c->g, fields_of<double>(c, c->cur), fields_of<double>(c, 1 - c->cur),
+                                                 coefficients<double>(q, b, 1.0), c->tile, c->stream)
+                      : launch_cool<double>(c->g, fields_of<double>(c, c->cur), fields_of<double>(c, 1 - c->cur),
+                                            moms_of<double>(c), coefficients<double>(q, b, 1.0), c->stream);
         else
-            e = launch_cool<float>(c->g, fields_of<float>(c, c->cur), fields_of<float>(c, 1 - c->cur),
-                                   moms_of<float>(c), coefficients<float>(q, b, 1.0), c->stream);
+            e = tiled ? launch_cool_tile<float>(c->g, fields_of<float>(c, c->cur), fields_of<float>(c, 1 - c->cur),
+                                                coefficients<float>(q, b, 1.0), c->tile, c->stream)
+                      : launch_cool<float>(c->g, fields_of<float>(c, c->cur), fields_of<float>(c, 1 - c->cur),
+                                           moms_of<float>(c), coefficients<float>(q, b, 1.0), c->stream);
         if (e != hipSuccess) return hipfail(c, e, "cooling kernel launch");
         c->cur = 1 - c->cur;
     }

@@ -91,6 +91,12 @@ bool tile_supported(TileShape ts);
 uint32_t tile_blocks(const Geom &g, TileShape ts);
 // With diag it also writes the phase arg(phi^n) of every site into
 // alpha[2][plane] (NaN where phi = 0), the winding kernel's input.
+// One forward-Euler step of the cooling flow with the tiled kernel: fields
+// `in` -> `out`, momenta untouched.
+template <typename T>
+hipError_t launch_cool_tile(const Geom &g, Fields<T> in, Fields<T> out, const StepCoef<T> &c, TileShape ts,
+                            hipStream_t st);
+
 // nt selects streaming (non-temporal) stores for the outputs.
 template <typename T>
 hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, const StepCoef<T> &c,

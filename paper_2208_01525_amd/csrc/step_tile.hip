@@ -57,8 +57,11 @@ __device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t nblk) {
 }
 
 // One tile (64 x TY columns, planes [Z0, Z0 + TZ)) of one box; accumulates the
-// integer-time sums of its interior sites into acc when DIAG.
-template <typename T, bool DIAG, int TY, bool NT>
+// integer-time sums of its interior sites into acc when DIAG.  With COOL the
+// fields move along their forces (one forward-Euler step of the cooling
+// flow, coefficients set by the caller) and the momenta are neither read nor
+// written.
+template <typename T, bool DIAG, int TY, bool NT, bool COOL = false>
 __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, const Fields<T> &out,
                                           const Moms<T> &mom, const StepCoef<T> &c, int X0, int Y0, int Z0, int TZ,
                                           Lds<T, TY> &L, double (&acc)[6], T *alpha, uint32_t plane) {
@@ -126,7 +129,7 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
         load_plane(wrapi(z + 1, g.nz), nf, nA, nU);
         cx<T> p0[2];
         T e0[2][3];
-        if (upd) {
+        if (upd && !COOL) {
 #pragma unroll
             for (int sec = 0; sec < 2; sec++) {
                 p0[sec] = mom.pi[sec][s];
@@ -201,9 +204,13 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                 F.im = c.inv_h2 * lap.im - br * f.im;
 
                 cx<T> p1;
-                p1.re = c.cpi * p0[sec].re + c.kpi * F.re;
-                p1.im = c.cpi * p0[sec].im + c.kpi * F.im;
-                st_stream<NT>(&mom.pi[sec][s], p1);
+                if constexpr (COOL) {
+                    p1 = F;                 // phi flows along its force
+                } else {
+                    p1.re = c.cpi * p0[sec].re + c.kpi * F.re;
+                    p1.im = c.cpi * p0[sec].im + c.kpi * F.im;
+                    st_stream<NT>(&mom.pi[sec][s], p1);
+                }
                 cx<T> fn;
                 fn.re = f.re + c.k * p1.re;
                 fn.im = f.im + c.k * p1.im;
@@ -217,12 +224,19 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                 const T My = -c.inv_h3 * ((sxy_mx - sxy) + (syz - syz_mz));
                 const T Mz = -c.inv_h3 * ((sxz_mx - sxz) + (syz_my - syz));
                 const T Jx = c.cur[sec] * imc(f, wx), Jy = c.cur[sec] * imc(f, wy), Jz = c.cur[sec] * imc(f, wz);
-                const T e1x = c.cE * e0[sec][0] + c.kE * (Mx + Jx);
-                const T e1y = c.cE * e0[sec][1] + c.kE * (My + Jy);
-                const T e1z = c.cE * e0[sec][2] + c.kE * (Mz + Jz);
-                st_stream<NT>(&mom.E[sec][0][s], e1x);
-                st_stream<NT>(&mom.E[sec][1][s], e1y);
-                st_stream<NT>(&mom.E[sec][2][s], e1z);
+                T e1x, e1y, e1z;
+                if constexpr (COOL) {
+                    e1x = Mx + Jx;          // the links flow along their force
+                    e1y = My + Jy;
+                    e1z = Mz + Jz;
+                } else {
+                    e1x = c.cE * e0[sec][0] + c.kE * (Mx + Jx);
+                    e1y = c.cE * e0[sec][1] + c.kE * (My + Jy);
+                    e1z = c.cE * e0[sec][2] + c.kE * (Mz + Jz);
+                    st_stream<NT>(&mom.E[sec][0][s], e1x);
+                    st_stream<NT>(&mom.E[sec][1][s], e1y);
+                    st_stream<NT>(&mom.E[sec][2][s], e1z);
+                }
                 st_stream<NT>(&out.A[sec][0][s], cA[sec][0] + c.k * e1x);
                 st_stream<NT>(&out.A[sec][1][s], cA[sec][1] + c.k * e1y);
                 st_stream<NT>(&out.A[sec][2][s], cA[sec][2] + c.k * e1z);
@@ -339,6 +353,37 @@ __global__ __launch_bounds__(64 * (TY + 3)) void step_tile_batch_kernel(const Ba
         block_sum_store<6, TY + 3>(acc, part, SL_EPS, lt);
     }
 }
+
+// One step of the cooling flow with the tiled kernel (momenta untouched).
+template <typename T, int TY>
+__global__ __launch_bounds__(64 * (TY + 3)) void cool_tile_kernel(Geom g, Fields<T> in, Fields<T> out, StepCoef<T> c,
+                                                                  int TZ, int ntx, int nty, int ntz) {
+    __shared__ Lds<T, TY> L;
+    const uint32_t t = xcd_order(blockIdx.x, (uint32_t)(ntx * nty * ntz));
+    const int tx = t % ntx, ty_ = (t / ntx) % nty, tz = t / (ntx * nty);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    const Moms<T> none{};
+    tile_step<T, false, TY, true, true>(g, in, out, none, c, tx * 64, ty_ * TY, tz * TZ, TZ, L, acc, nullptr, 0);
+}
+
+template <typename T>
+hipError_t launch_cool_tile(const Geom &g, Fields<T> in, Fields<T> out, const StepCoef<T> &c, TileShape ts,
+                            hipStream_t st) {
+    const int ntx = (g.nx + 63) / 64, nty = (g.ny + ts.ty - 1) / ts.ty, ntz = (g.nz + ts.tz - 1) / ts.tz;
+    const dim3 grid((unsigned)(ntx * nty * ntz), 1, 1);
+    switch (ts.ty) {
+        case 4: cool_tile_kernel<T, 4><<<grid, dim3(64, 7, 1), 0, st>>>(g, in, out, c, ts.tz, ntx, nty, ntz); break;
+        case 8: cool_tile_kernel<T, 8><<<grid, dim3(64, 11, 1), 0, st>>>(g, in, out, c, ts.tz, ntx, nty, ntz); break;
+        case 12: cool_tile_kernel<T, 12><<<grid, dim3(64, 15, 1), 0, st>>>(g, in, out, c, ts.tz, ntx, nty, ntz); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_cool_tile<float>(const Geom &, Fields<float>, Fields<float>, const StepCoef<float> &,
+                                            TileShape, hipStream_t);
+template hipError_t launch_cool_tile<double>(const Geom &, Fields<double>, Fields<double>, const StepCoef<double> &,
+                                             TileShape, hipStream_t);
 
 bool tile_supported(TileShape ts) { return (ts.ty == 4 || ts.ty == 8 || ts.ty == 12) && ts.tz >= 1; }
 

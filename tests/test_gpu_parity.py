@@ -389,15 +389,18 @@ def test_full_size_workload_sampled():
     assert r["wind_abs"][0] == np.abs(W_all[:3]).sum() and r["wind_abs"][1] == np.abs(W_all[3:]).sum()
 
 
+@pytest.mark.parametrize("tile", [(8, 32), (12, 5), (0, 8)])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_cooling_parity(precision):
+def test_cooling_parity(precision, tile):
     """Diffusive cooling (Sec. III) on the GPU against the oracle: 30 steps of 1/30 from
-    random phases and random links."""
+    random phases, random links and random momenta (which cooling leaves untouched), with
+    the tiled kernel (ragged tiles included) and the per-site kernel."""
     nx, ny, nz = 40, 12, 9
-    st = I.random_phase(nx, ny, nz, 31)
-    st[I.A:I.A + 6] = I.random_full(nx, ny, nz, 32, link=0.4)[I.A:I.A + 6]
+    st = I.random_full(nx, ny, nz, 32, link=0.4, mom=0.5)
+    st[:4] = I.random_phase(nx, ny, nz, 31)[:4]
     st = rounded(st, precision)
     lat = lattice(nx, ny, nz, precision, eta_ref=4.0, kappa=0.9)
+    lat.set_tile(*tile)
     lat.set_fields(st)
     lat.cool(30, 1.0 / 30.0)
     got = lat.get_fields()
@@ -408,6 +411,7 @@ def test_cooling_parity(precision):
     O.cool(m, b, 30, 1.0 / 30.0)
     err = np.abs(got - ref).max()
     assert err <= tolerance(np.abs(b - ref).max(), 30, ref, precision), err
+    assert np.array_equal(got[I.PI:I.A], st[I.PI:I.A]) and np.array_equal(got[I.E:], st[I.E:])
     with pytest.raises(P.MtsError) as e:
         lat.cool(1, 0.1)          # 0.1 (48 + 3.8) > 2: forward Euler unstable
     assert e.value.code == -2

@@ -7,10 +7,14 @@ kappa = 0.9, seeded random-phase initial conditions, FP32 fields with FP64
 reductions, a = 1 at eta = 128.  Warm-up steps run from eta = 1; the timed
 steps continue the same run (the default 10 + 1260 steps reach eta = 128).
 
-Printed: one JSON line with site-updates/s, the HBM roofline of the update
-kernel (timed with HIP events around each launch on the library's stream),
-an FP64 leg of the same box, and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+Printed: one JSON line with site-updates/s (`value`: whole steps, the
+diagnostic steps included; `pure_step_value`: from the update kernel's time
+alone), the HBM roofline of the update kernel (timed with HIP events around
+each launch on the library's stream; `box_ceiling`: this box's rate for a
+plain copy and for the update's access pattern without its stencil,
+measured by the library's bandwidth probe), an FP64 leg of the same box,
+the batched ensemble, and the FP64 CPU oracle timed on a bounded sample of
+the same workload.
 """
 import argparse
 import json
@@ -68,6 +72,7 @@ def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0
             lat.set_streaming_stores(bool(tile[2]))
     else:
         tuned = lat.autotune(4)      # times every tile shape on this machine (leaves seed-0 fields)
+    ceiling = lat.bandwidth_probe(5)  # this box's copy rate and the update pattern's rate (overwrites)
     lat.init_fields(seed)
     lat.step(warmup, eta0, era_m, s)
     lat.diagnostics()
@@ -95,7 +100,10 @@ def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(n, precision, lat.get_tile(), lat.get_streaming_stores()),
-                     "algorithmic_bytes": BYTES_PER_SITE[precision] * sites},
+                     "algorithmic_bytes": BYTES_PER_SITE[precision] * sites,
+                     "box_ceiling": {**{k: round(v, 1) for k, v in ceiling.items()},
+                                     "frac_of_pattern": achieved / ceiling["pattern_GBps"]}},
+        "pure_step_value": sites / (kern_ms * 1e-3),
         "tile": lat.get_tile(),
         "streaming_stores": lat.get_streaming_stores(),
         "autotune_ms_per_step": tuned[2] if tuned else None,
@@ -241,6 +249,7 @@ def main():
         "roofline": fp32["roofline"],
         "cpu_baseline": cpu,
         "kernel_ms": fp32["kernel_ms"],
+        "pure_step_value": fp32["pure_step_value"],
         "tile": fp32["tile"],
         "streaming_stores": fp32["streaming_stores"],
         "diag_step_kernel_ms": fp32["diag_step_kernel_ms"],

@@ -237,6 +237,17 @@ int mts_get_streaming_stores(const mts_ctx *ctx, int32_t *on);
  * conditions): call it before mts_init_fields / mts_set_fields. */
 int mts_autotune(mts_ctx *ctx, int32_t steps, int32_t *ty, int32_t *tz, double *ms_per_step);
 
+/* Bandwidth probe (a measurement aid, not part of the method): on this
+ * context's state buffer, time `reps` launches each of (a) a plain device
+ * copy of one field copy onto the other, one float4 per thread, and (b) a
+ * kernel with exactly the update's HBM traffic and none of its stencil or
+ * arithmetic (per site the 10 momentum values read and rewritten in place,
+ * the 10 field values read and written to the other copy, in the context's
+ * store mode), with HIP events; reports bytes moved / time in GB/s.  (b) is
+ * the rate the update kernel could reach on this machine.  The lattice is
+ * overwritten (as by mts_autotune): call it before mts_init_fields. */
+int mts_bandwidth_probe(mts_ctx *ctx, int32_t reps, double *copy_gbps, double *pattern_gbps);
+
 /* Kernel timing with HIP events on the context's stream.  While enabled,
  * every launch of the update kernel is bracketed by events; the summary
  * returns the launch count and the summed event time in milliseconds of

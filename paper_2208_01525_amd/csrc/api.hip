@@ -739,6 +739,42 @@ int mts_get_tile(const mts_ctx *c, int32_t *ty, int32_t *tz) {
     return MTS_OK;
 }
 
+int mts_bandwidth_probe(mts_ctx *c, int32_t reps, double *copy_gbps, double *pattern_gbps) {
+    if (!c || reps < 1 || !copy_gbps || !pattern_gbps) return MTS_EINVAL;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    const uint64_t copy_bytes = (uint64_t)10 * c->plane * c->esz;   // one field copy onto the other
+    const double pattern_bytes = (double)(c->esz * 40) * (double)c->S;
+    auto run = [&](auto launch, double bytes, double *out) -> int {
+        hipError_t e = launch();                                    // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+        for (int r = 0; e == hipSuccess && r < reps; r++) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) return hipfail(c, e, "bandwidth probe");
+        *out = bytes * reps / (ms * 1e-3) / 1e9;
+        return MTS_OK;
+    };
+    int rc = run([&] { return launch_probe_copy(c->state, copy_bytes, c->stream); }, 2.0 * (double)copy_bytes,
+                 copy_gbps);
+    if (rc == MTS_OK) {
+        if (c->p.precision == MTS_FP64)
+            rc = run([&] { return launch_probe_pattern<double>(reinterpret_cast<double *>(c->state), c->plane,
+                                                               (uint32_t)c->S, c->cur, c->nt, c->stream); },
+                     pattern_bytes, pattern_gbps);
+        else
+            rc = run([&] { return launch_probe_pattern<float>(reinterpret_cast<float *>(c->state), c->plane,
+                                                              (uint32_t)c->S, c->cur, c->nt, c->stream); },
+                     pattern_bytes, pattern_gbps);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
 int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, double *ms_out) {
     if (!c || steps < 1) return MTS_EINVAL;
     const std::vector<int> tys = c->p.precision == MTS_FP64 ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 12};

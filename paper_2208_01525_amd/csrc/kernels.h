@@ -91,6 +91,12 @@ bool tile_supported(TileShape ts);
 uint32_t tile_blocks(const Geom &g, TileShape ts);
 // With diag it also writes the phase arg(phi^n) of every site into
 // alpha[2][plane] (NaN where phi = 0), the winding kernel's input.
+// Bandwidth probes on a state buffer: a copy of the first `bytes_per_copy`
+// bytes onto the next ones, and the update's access pattern (no stencil).
+hipError_t launch_probe_copy(void *state, uint64_t bytes_per_copy, hipStream_t st);
+template <typename T>
+hipError_t launch_probe_pattern(T *state, uint64_t plane, uint32_t S, int in, bool nt, hipStream_t st);
+
 // One forward-Euler step of the cooling flow with the tiled kernel: fields
 // `in` -> `out`, momenta untouched.
 template <typename T>

@@ -18,7 +18,7 @@ MTS_OK, MTS_EINVAL, MTS_EUNSTABLE, MTS_ENOMEM, MTS_EHIP, MTS_ENONFINITE = 0, -1,
 MTS_FP32, MTS_FP64 = 1, 2
 
 EXPORTS = ("mts_state_bytes", "mts_create", "mts_destroy", "mts_init_fields", "mts_step", "mts_cool", "mts_diagnostics",
-           "mts_get_fields", "mts_set_fields", "mts_get_windings", "mts_get_cells", "mts_get_sites", "mts_segments", "mts_set_tile", "mts_get_tile", "mts_set_streaming_stores", "mts_get_streaming_stores", "mts_autotune", "mts_timing_enable",
+           "mts_get_fields", "mts_set_fields", "mts_get_windings", "mts_get_cells", "mts_get_sites", "mts_segments", "mts_set_tile", "mts_get_tile", "mts_set_streaming_stores", "mts_bandwidth_probe", "mts_get_streaming_stores", "mts_autotune", "mts_timing_enable",
            "mts_timing_read", "mts_last_error", "mts_strerror",
            "mts_batch_state_bytes", "mts_batch_create", "mts_batch_destroy", "mts_batch_size",
            "mts_batch_init_fields", "mts_batch_step", "mts_batch_diagnostics", "mts_batch_get_fields",
@@ -107,6 +107,8 @@ def load():
     L.mts_get_sites.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
     L.mts_set_tile.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     L.mts_set_streaming_stores.argtypes = [vp, ctypes.c_int32]
+    L.mts_bandwidth_probe.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double)]
     L.mts_batch_set_streaming_stores.argtypes = [vp, ctypes.c_int32]
     L.mts_get_streaming_stores.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.mts_batch_get_streaming_stores.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
@@ -270,6 +272,13 @@ class Lattice:
 
     def set_streaming_stores(self, on):
         self._check(self.L.mts_set_streaming_stores(self.ctx, 1 if on else 0))
+
+    def bandwidth_probe(self, reps=5):
+        """GB/s of a plain copy and of the update's access pattern on this machine (overwrites
+        the lattice)."""
+        cp, pt = ctypes.c_double(), ctypes.c_double()
+        self._check(self.L.mts_bandwidth_probe(self.ctx, int(reps), ctypes.byref(cp), ctypes.byref(pt)))
+        return {"copy_GBps": cp.value, "pattern_GBps": pt.value}
 
     def get_streaming_stores(self):
         v = ctypes.c_int32()

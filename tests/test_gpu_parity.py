@@ -538,3 +538,17 @@ def test_1280_workload_sampled():
     lat.close()
     del lat
     torch.cuda.empty_cache()
+
+
+def test_bandwidth_probe_reports_rates():
+    """The bandwidth probe times a copy and the update's access pattern on the context's
+    buffer: positive, finite rates below the HBM peak (a box of 64 MB: HBM, not cache)."""
+    lat = lattice(256, 256, 64, "fp32", eta_ref=4.0)
+    r = lat.bandwidth_probe(3)
+    for k in ("copy_GBps", "pattern_GBps"):
+        assert 100.0 < r[k] < 20000.0, r
+    lat.init_fields(1)                     # the lattice is usable afterwards
+    lat.step(2, 1.0, 0.5, 1.0)
+    assert np.isfinite(lat.get_sites(np.arange(8, dtype=np.uint64))).all()
+    with pytest.raises(P.MtsError):
+        lat.bandwidth_probe(0)

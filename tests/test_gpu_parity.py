@@ -552,3 +552,48 @@ def test_bandwidth_probe_reports_rates():
     assert np.isfinite(lat.get_sites(np.arange(8, dtype=np.uint64))).all()
     with pytest.raises(P.MtsError):
         lat.bandwidth_probe(0)
+
+
+def test_full_size_ensemble_sampled():
+    """The benchmarked ensemble at full size and in its launch configuration: 48 boxes of
+    128^3 and 16 of 256^3 (seeds 1000 + b, m = 1/2 or 2/3, s = 0 or 1 by box), the
+    autotuner's tile shape and store mode, one graph launch for 10 steps, then one more
+    step checked at sampled sites of four boxes against the oracle's step on 5^3 patches."""
+    torch.cuda.empty_cache()
+    nb, small = 64, 48
+    params = [P.make_params(128 if b < small else 256, precision="fp32", eta_ref=41.0, diag_every=10)
+              for b in range(nb)]
+    need = sum(P.state_bytes(p) for p in params) * 1.15
+    if torch.cuda.mem_get_info()[0] < need:
+        pytest.skip(f"needs {need / 1e9:.0f} GB free on the device")
+    era = [0.5 if b % 2 == 0 else 2.0 / 3.0 for b in range(nb)]
+    sv = [0.0 if (b // 2) % 2 == 0 else 1.0 for b in range(nb)]
+    bt = P.Batch(params)
+    bt.autotune(3)
+    bt.init_fields([1000 + b for b in range(nb)])
+    bt.step(10, [1.0] * nb, era, sv)
+    boxes = (0, 47, 49, 62)                  # 128^3 radiation / matter, 256^3 matter / radiation
+    before = {k: bt.get_fields(k) for k in boxes}
+    bt.step(1, [2.0] * nb, era, sv)
+    rng = np.random.default_rng(5)
+    for k in boxes:
+        n = params[k].nx
+        after = bt.get_fields(k)
+        samples = [(0, 0, 0), (n - 1, n - 1, n - 1), (31, 11, 63), (32, 12, 64)]
+        samples += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(6)]
+        m = O.model(5, eta_ref=41.0)
+        for c in samples:
+            z0, y0, x0 = c
+            idx = np.ix_(np.arange(z0 - 2, z0 + 3) % n, np.arange(y0 - 2, y0 + 3) % n, np.arange(x0 - 2, x0 + 3) % n)
+            st = np.ascontiguousarray(np.stack([before[k][q][idx] for q in range(20)]))
+            O.step(m, st, 2.0, era[k], sv[k])
+            got = after[:, z0, y0, x0]
+            err = np.abs(st[:, 2, 2, 2] - got).max()
+            assert err <= 64 * U["fp32"] * max(1.0, np.abs(st[:, 2, 2, 2]).max()), (k, c, err)
+        recs = bt.diagnostics(k)
+        assert [r["step"] for r in recs] == [0, 10] and all(r["flags"] == 0 for r in recs)
+        if sv[k] == 0.0:
+            assert max(recs[-1]["gauss_rel"]) < 2e-5
+    bt.close()
+    del bt
+    torch.cuda.empty_cache()

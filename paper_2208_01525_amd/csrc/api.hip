@@ -1005,6 +1005,31 @@ int batch_step_t(mts_batch *b, int32_t n, const double *eta0, const double *era_
     batch_collect_timing(b);
     batch_release_graph(b);
 
+    // Host bookkeeping advances while the steps are captured; nothing runs
+    // until the graph is launched, so a failure before that restores it.
+    struct Saved {
+        int cur;
+        int64_t step_count, produced, cells_step;
+        size_t nmeta;
+        bool have_cells;
+    };
+    std::vector<Saved> saved;
+    for (mts_ctx *c : b->box)
+        saved.push_back({c->cur, c->step_count, c->produced, c->cells_step, c->meta.size(), c->have_cells});
+    auto rollback = [&](int code, const std::string &why) {
+        for (size_t k = 0; k < nbox; k++) {
+            mts_ctx *c = b->box[k];
+            c->cur = saved[k].cur;
+            c->step_count = saved[k].step_count;
+            c->produced = saved[k].produced;
+            c->cells_step = saved[k].cells_step;
+            c->meta.resize(saved[k].nmeta);
+            c->have_cells = saved[k].have_cells;
+        }
+        batch_release_graph(b);
+        return bfail(b, code, why);
+    };
+
     // join the caller's stream, capture all n steps, launch once, join back
     BHIPCHK(b, hipEventRecord(b->ev_in, b->user));
     BHIPCHK(b, hipStreamWaitEvent(b->stream, b->ev_in, 0));
@@ -1031,13 +1056,15 @@ int batch_step_t(mts_batch *b, int32_t n, const double *eta0, const double *era_
     const hipError_t ec = hipStreamEndCapture(b->stream, &g);
     if (err != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
-        return bfail(b, MTS_EHIP, std::string("batch capture: ") + hipGetErrorString(err));
+        return rollback(MTS_EHIP, std::string("batch capture: ") + hipGetErrorString(err));
     }
-    if (ec != hipSuccess) return bfail(b, MTS_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    if (ec != hipSuccess) return rollback(MTS_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
     b->graph = g;
-    BHIPCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-    BHIPCHK(b, hipEventRecord(b->ev_t0, b->stream));
-    BHIPCHK(b, hipGraphLaunch(b->exec, b->stream));
+    hipError_t el = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (el != hipSuccess) return rollback(MTS_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(el));
+    el = hipEventRecord(b->ev_t0, b->stream);
+    if (el == hipSuccess) el = hipGraphLaunch(b->exec, b->stream);
+    if (el != hipSuccess) return rollback(MTS_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(el));
     BHIPCHK(b, hipEventRecord(b->ev_t1, b->stream));
     b->t_pending = true;
     b->t_pending_steps = n;

@@ -285,13 +285,15 @@ int do_step(mts_ctx *c, int32_t n, double eta, double era_m, double s) {
                                                      c->stream);
             if (e != hipSuccess) return hipfail(c, e, "step kernel launch");
         }
+        // the step is enqueued: the bookkeeping advances even if its diagnostics fail
+        hipError_t ep = hipSuccess;
         if (diag) {
             TimedRegion tr(c, 2);
-            hipError_t e = enqueue_diag_post<T>(c, b, eta_j, s, c->stream, c->tile.ty != 0);
-            if (e != hipSuccess) return hipfail(c, e, "diagnostic kernel launch");
+            ep = enqueue_diag_post<T>(c, b, eta_j, s, c->stream, c->tile.ty != 0);
         }
         c->cur = 1 - c->cur;
         c->step_count++;
+        if (ep != hipSuccess) return hipfail(c, ep, "diagnostic kernel launch");
     }
     return MTS_OK;
 }

@@ -744,8 +744,12 @@ int mts_get_tile(const mts_ctx *c, int32_t *ty, int32_t *tz) {
 int mts_bandwidth_probe(mts_ctx *c, int32_t reps, double *copy_gbps, double *pattern_gbps) {
     if (!c || reps < 1 || !copy_gbps || !pattern_gbps) return MTS_EINVAL;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
+    hipError_t ec = hipEventCreate(&e0);
+    if (ec == hipSuccess) ec = hipEventCreate(&e1);
+    if (ec != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hipfail(c, ec, "hipEventCreate");
+    }
     const uint64_t copy_bytes = (uint64_t)10 * c->plane * c->esz;   // one field copy onto the other
     const double pattern_bytes = (double)(c->esz * 40) * (double)c->S;
     auto run = [&](auto launch, double bytes, double *out) -> int {
@@ -781,15 +785,23 @@ int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, do
     if (!c || steps < 1) return MTS_EINVAL;
     const std::vector<int> tys = c->p.precision == MTS_FP64 ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 12};
     const int tzs[] = {8, 16, 32, 64};
+    // time the plain update, outside the caller's timing; every exit below
+    // restores these settings
     const int32_t d = c->p.diag_every;
-    c->p.diag_every = 0;                       // time the plain update
+    const bool timing = c->timing;
+    c->p.diag_every = 0;
+    c->timing = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIPCHK(c, hipEventCreate(&e0));
-    HIPCHK(c, hipEventCreate(&e1));
+    int rc = MTS_OK;
+    auto hip = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess && rc == MTS_OK) rc = hipfail(c, e, what);
+        return rc == MTS_OK;
+    };
+    hip(hipEventCreate(&e0), "hipEventCreate") && hip(hipEventCreate(&e1), "hipEventCreate");
     double best = INFINITY;
     TileShape pick = c->tile;
     bool pick_nt = c->nt;
-    int rc = mts_init_fields(c, 0);
+    if (rc == MTS_OK) rc = mts_init_fields(c, 0);
     for (int nt = 0; nt < 2; nt++)
     for (int ty : tys) {
         for (int tz : tzs) {
@@ -798,12 +810,13 @@ int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, do
             c->nt = nt != 0;
             if ((rc = mts_set_tile(c, ty, tz)) != MTS_OK) break;
             if ((rc = mts_step(c, 1, 1.0, 0.5, 1.0)) != MTS_OK) break;       // warm
-            HIPCHK(c, hipEventRecord(e0, c->stream));
+            if (!hip(hipEventRecord(e0, c->stream), "hipEventRecord")) break;
             if ((rc = mts_step(c, steps, 1.1, 0.5, 1.0)) != MTS_OK) break;
-            HIPCHK(c, hipEventRecord(e1, c->stream));
-            HIPCHK(c, hipEventSynchronize(e1));
             float ms = 0;
-            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+            if (!(hip(hipEventRecord(e1, c->stream), "hipEventRecord") &&
+                  hip(hipEventSynchronize(e1), "hipEventSynchronize") &&
+                  hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime")))
+                break;
             if (ms < best) {
                 best = ms;
                 pick = TileShape{ty, tz};
@@ -812,9 +825,10 @@ int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, do
         }
     }
     c->nt = pick_nt;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     c->p.diag_every = d;
+    c->timing = timing;
     if (rc != MTS_OK) return rc;
     if ((rc = mts_set_tile(c, pick.ty, pick.tz)) != MTS_OK) return rc;
     if ((rc = mts_init_fields(c, 0)) != MTS_OK) return rc;

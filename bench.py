@@ -155,11 +155,11 @@ def run_batch(P, torch, steps, small=48, big=16, tune_steps=3):
 
 def cpu_baseline():
     """The FP64 oracle on a bounded sample of the workload: a 128^3 box with the same
-    schedule (radiation era, s = 1, a = 1 at eta = 128), 20 steps with the diagnostics
-    every 10th step, on all host threads OpenMP gives it."""
+    schedule (radiation era, s = 1, a = 1 at eta = 128), 80 steps with the diagnostics
+    every 10th step (about 15 s of CPU work), on all host threads OpenMP gives it."""
     import oracle as O
 
-    n, steps = 128, 20
+    n, steps = 128, 80
     m = O.model(n, eta_ref=128.0)
     st = O.init_random_phase(m, 1)
     t0 = time.perf_counter()

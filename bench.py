@@ -31,7 +31,8 @@ BYTES_PER_SITE = {"fp32": 160, "fp64": 320}   # 20 reals read + 20 written per s
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_tile_512.txt")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2208_01525_amd", "csrc", f) for f in ("step_tile.hip", "device.h", "kernels.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2208_01525_amd", "csrc", f)
+                  for f in ("step_tile.hip", "site.h", "device.h", "kernels.h")]
 
 
 def kernel_source_hash():
@@ -89,23 +90,32 @@ def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0
     lat.timing_enable(False)
     sites = n ** 3
     wall = t1 - t0
-    kern_ms = tm["ms_plain"] / max(tm["n_plain"], 1)
-    achieved = BYTES_PER_SITE[precision] * sites / (kern_ms * 1e-3) / 1e9
+    # the dominant update kernel: one step per launch, or two with time blocking
+    tblock = lat.get_time_blocking()
+    if tm["ms_pair"] > tm["ms_plain"]:
+        launch_ms, per_launch, kname = tm["ms_pair"] / tm["n_pair"], 2, "step_pair_kernel"
+    else:
+        launch_ms, per_launch, kname = tm["ms_plain"] / max(tm["n_plain"], 1), 1, "step_tile_kernel"
+    kern_ms = launch_ms / per_launch
+    achieved = BYTES_PER_SITE[precision] * sites * per_launch / (launch_ms * 1e-3) / 1e9
     out = {
         "value": sites * steps / wall,
         "ms_per_step": 1e3 * wall / steps,
         "kernel_ms": kern_ms,
         "diag_step_kernel_ms": tm["ms_diag"] / max(tm["n_diag"], 1),
         "diag_post_ms": tm["ms_post"] / max(tm["n_diag"], 1),
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "roofline": {"bound": "hbm", "kernel": kname, "steps_per_launch": per_launch,
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(n, precision, lat.get_tile(), lat.get_streaming_stores()),
+                     "traffic": measured_traffic(n, precision, lat.get_tile(), lat.get_streaming_stores())
+                     if per_launch == 1 else None,
                      "algorithmic_bytes": BYTES_PER_SITE[precision] * sites,
                      "box_ceiling": {**{k: round(v, 1) for k, v in ceiling.items()},
                                      "frac_of_pattern": achieved / ceiling["pattern_GBps"]}},
         "pure_step_value": sites / (kern_ms * 1e-3),
         "tile": lat.get_tile(),
         "streaming_stores": lat.get_streaming_stores(),
+        "time_blocking": {"steps_per_sweep": tblock[0], "tile": list(tblock[1:])},
         "autotune_ms_per_step": tuned[2] if tuned else None,
         "last_record": {k: recs[-1][k] for k in ("eta", "xi_W", "xi_lag", "v2_lag", "f_total", "gauss_rel")}
         if recs else None,
@@ -252,6 +262,7 @@ def main():
         "pure_step_value": fp32["pure_step_value"],
         "tile": fp32["tile"],
         "streaming_stores": fp32["streaming_stores"],
+        "time_blocking": fp32["time_blocking"],
         "diag_step_kernel_ms": fp32["diag_step_kernel_ms"],
         "diag_post_ms": fp32["diag_post_ms"],
         "fp64": {"value": fp64["value"], "unit": "site-updates/s", "steps": args.fp64_steps,

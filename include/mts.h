@@ -228,13 +228,32 @@ int mts_get_tile(const mts_ctx *ctx, int32_t *ty, int32_t *tz);
 int mts_set_streaming_stores(mts_ctx *ctx, int32_t on);
 int mts_get_streaming_stores(const mts_ctx *ctx, int32_t *on);
 
+/* Temporal blocking (FP32): with steps = 2, every two consecutive plain
+ * steps (no diagnostics due at either) run as one sweep of a two-level
+ * tiled kernel (tiles of 64 x ty sites, ty in {3, 7}, tz >= 1 planes per
+ * workgroup) that reads the state at step n from HBM once and writes the
+ * state at step n + 2 once: half the HBM traffic per step.  The fields and
+ * momenta are bitwise identical to those of single steps.  The momenta then
+ * alternate between the state buffer and a second momentum copy that the
+ * library allocates on the first call (10 planes, 40 bytes per site; freed
+ * by mts_destroy); MTS_ENOMEM if it does not fit, and the context stays at
+ * one step per sweep.  steps = 1 (the default) is one step per sweep.
+ * EINVAL for FP64, other steps or tile shapes.  Synchronises the stream.
+ * Update of Sec. III (the same equations as mts_step). */
+int mts_set_time_blocking(mts_ctx *ctx, int32_t steps, int32_t ty, int32_t tz);
+int mts_get_time_blocking(const mts_ctx *ctx, int32_t *steps, int32_t *ty, int32_t *tz);
+
 /* Autotuner: time `steps` plain steps of every supported tile shape
  * (ty in {4, 8, 12} -- {4, 8} in FP64 -- by tz in {8, 16, 32, 64}, with and
  * without streaming stores) on this
  * box with HIP events, keep the fastest, and report it (and its ms per
- * step).  The choice changes speed only: results are bitwise identical for
- * every shape.  Overwrites the lattice (it is left at seed-0 initial
- * conditions): call it before mts_init_fields / mts_set_fields. */
+ * step).  In FP32 it then times the two-step kernel (ty in {3, 7} by the
+ * same tz and store modes, over an even number of steps) and switches
+ * time blocking on if that is faster per step (mts_get_time_blocking tells
+ * which; ms_per_step is the best of both).  The choice changes speed only:
+ * results are bitwise identical for every shape and mode.  Overwrites the
+ * lattice (it is left at seed-0 initial conditions): call it before
+ * mts_init_fields / mts_set_fields. */
 int mts_autotune(mts_ctx *ctx, int32_t steps, int32_t *ty, int32_t *tz, double *ms_per_step);
 
 /* Bandwidth probe (a measurement aid, not part of the method): on this
@@ -251,12 +270,14 @@ int mts_bandwidth_probe(mts_ctx *ctx, int32_t reps, double *copy_gbps, double *p
 /* Kernel timing with HIP events on the context's stream.  While enabled,
  * every launch of the update kernel is bracketed by events; the summary
  * returns the launch count and the summed event time in milliseconds of
- * plain steps and of diagnostic steps, and the summed time of the
- * diagnostic post-kernels (windings/Gauss, cells, overlap, final reduce).
- * mts_timing_read synchronises the stream and resets the counters. */
+ * plain steps, of diagnostic steps and of two-step sweeps (n_pair launches,
+ * each advancing two steps), and the summed time of the diagnostic
+ * post-kernels (windings/Gauss, cells, overlap, final reduce).  Any output
+ * pointer may be NULL.  mts_timing_read synchronises the stream and resets
+ * the counters. */
 int mts_timing_enable(mts_ctx *ctx, int32_t on);
 int mts_timing_read(mts_ctx *ctx, int64_t *n_plain, double *ms_plain, int64_t *n_diag, double *ms_diag,
-                    double *ms_post);
+                    double *ms_post, int64_t *n_pair, double *ms_pair);
 
 /* ------------------------------------------------------------ ensembles
  * A batch advances several independent boxes (own size, couplings,

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmts.so")
-SOURCES = ["kernels.hip", "step_tile.hip", "diag.hip", "segments.hip", "probe.hip", "api.hip"]
+SOURCES = ["kernels.hip", "step_tile.hip", "step_pair.hip", "diag.hip", "segments.hip", "probe.hip", "api.hip"]
 ARCH = os.environ.get("MTS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

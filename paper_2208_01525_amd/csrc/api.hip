@@ -41,6 +41,10 @@ struct mts_ctx {
     uint32_t *nblk_dev = nullptr;
     TileShape tile{8, 32};       // ty = 0: per-site kernel
     bool nt = true;              // streaming stores in the tiled update
+    int tblock = 1;              // leapfrog steps per sweep through HBM (1, or 2: two-step kernel)
+    TileShape tile2{7, 32};      // tile of the two-step kernel
+    void *mom2 = nullptr;        // second momentum copy (10 planes), allocated for two-step sweeps
+    int mcur = 0;                // which momentum copy is current: 0 = the state buffer, 1 = mom2
     void *alpha = nullptr;       // arg(phi) per sector: T[2][plane]
     uint8_t *wabs = nullptr;     // packed |W| per sector: [2][plane]
     uint8_t *cells = nullptr;    // cell values per sector: [2][plane]
@@ -55,7 +59,7 @@ struct mts_ctx {
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     struct Mark {
-        int kind;                // 0 plain step, 1 diagnostic step, 2 diagnostic post-kernels
+        int kind;                // 0 plain step, 1 diagnostic step, 2 diagnostic post-kernels, 3 two-step sweep
         int a, b;                // event indices
     };
     std::vector<Mark> marks;
@@ -92,9 +96,27 @@ Fields<T> fields_of(const mts_ctx *c, int copy) {
     return f;
 }
 
+// Momentum copy `which` (0: planes 20..29 of the state buffer, 1: mom2).
+template <typename T>
+T *mom_base(const mts_ctx *c, int which) {
+    return which == 0 ? reinterpret_cast<T *>(c->state) + (size_t)20 * c->plane : static_cast<T *>(c->mom2);
+}
+
+template <typename T>
+Moms<T> moms_at(const mts_ctx *c, int which) {
+    T *base = mom_base<T>(c, which);
+    Moms<T> m;
+    for (int sec = 0; sec < 2; sec++) {
+        m.pi[sec] = reinterpret_cast<cx<T> *>(base + (size_t)(2 * sec) * c->plane);
+        for (int i = 0; i < 3; i++) m.E[sec][i] = base + (size_t)(4 + 3 * sec + i) * c->plane;
+    }
+    return m;
+}
+
+// The current momenta.
 template <typename T>
 Moms<T> moms_of(const mts_ctx *c) {
-    T *base = reinterpret_cast<T *>(c->state) + (size_t)20 * c->plane;
+    T *base = mom_base<T>(c, c->mcur);
     Moms<T> m;
     for (int sec = 0; sec < 2; sec++) {
         m.pi[sec] = reinterpret_cast<cx<T> *>(base + (size_t)(2 * sec) * c->plane);
@@ -267,13 +289,31 @@ hipError_t enqueue_diag_post(mts_ctx *c, const Book &b, double eta_j, double s, 
 template <typename T>
 int do_step(mts_ctx *c, int32_t n, double eta, double era_m, double s) {
     const mts_params &p = c->p;
-    Moms<T> mom = moms_of<T>(c);
     Partials part{c->partials, c->maxblk};
-    for (int32_t j = 0; j < n; j++) {
+    auto diag_due = [&](int64_t step) { return p.diag_every > 0 && (step % p.diag_every) == 0; };
+    for (int32_t j = 0; j < n;) {
         const double eta_j = eta + j * p.dt;
         const Book b = bookkeeping(p, eta_j, era_m, s);
         const StepCoef<T> coef = coefficients<T>(p, b, s);
-        const bool diag = p.diag_every > 0 && (c->step_count % p.diag_every) == 0;
+        const bool diag = diag_due(c->step_count);
+        if (c->tblock == 2 && !diag && j + 1 < n && !diag_due(c->step_count + 1)) {
+            // two plain steps in one sweep: fields to the other copy, momenta to the other copy
+            const double eta_k = eta + (j + 1) * p.dt;
+            const StepCoef<T> coef2 = coefficients<T>(p, bookkeeping(p, eta_k, era_m, s), s);
+            {
+                TimedRegion tr(c, 3);
+                hipError_t e = launch_step_pair<T>(c->g, fields_of<T>(c, c->cur), fields_of<T>(c, 1 - c->cur),
+                                                   moms_at<T>(c, c->mcur), moms_at<T>(c, 1 - c->mcur), coef, coef2,
+                                                   c->tile2, c->nt, c->stream);
+                if (e != hipSuccess) return hipfail(c, e, "two-step kernel launch");
+            }
+            c->cur = 1 - c->cur;
+            c->mcur = 1 - c->mcur;
+            c->step_count += 2;
+            j += 2;
+            continue;
+        }
+        Moms<T> mom = moms_of<T>(c);
         Fields<T> in = fields_of<T>(c, c->cur), out = fields_of<T>(c, 1 - c->cur);
         {
             TimedRegion tr(c, diag ? 1 : 0);
@@ -293,6 +333,7 @@ int do_step(mts_ctx *c, int32_t n, double eta, double era_m, double s) {
         }
         c->cur = 1 - c->cur;
         c->step_count++;
+        j++;
         if (ep != hipSuccess) return hipfail(c, ep, "diagnostic kernel launch");
     }
     return MTS_OK;
@@ -393,7 +434,7 @@ int get_fields_t(mts_ctx *c, double *host) {
     T *base = reinterpret_cast<T *>(c->state);
     HIPCHK(c, hipMemcpyAsync(buf.data(), base + (size_t)c->cur * 10 * c->plane, 10 * c->plane * sizeof(T),
                              hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(buf.data() + 10 * c->plane, base + 20 * c->plane, 10 * c->plane * sizeof(T),
+    HIPCHK(c, hipMemcpyAsync(buf.data() + 10 * c->plane, mom_base<T>(c, c->mcur), 10 * c->plane * sizeof(T),
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     to_host<T>(c, buf, host);
@@ -408,7 +449,7 @@ int set_fields_t(mts_ctx *c, const double *host) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpyAsync(base + (size_t)c->cur * 10 * c->plane, buf.data(), 10 * c->plane * sizeof(T),
                              hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(base + 20 * c->plane, buf.data() + 10 * c->plane, 10 * c->plane * sizeof(T),
+    HIPCHK(c, hipMemcpyAsync(mom_base<T>(c, c->mcur), buf.data() + 10 * c->plane, 10 * c->plane * sizeof(T),
                              hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return MTS_OK;
@@ -503,6 +544,7 @@ int mts_destroy(mts_ctx *c) {
     (void)hipFree(c->alpha);
     (void)hipFree(c->bits);
     (void)hipFree(c->ring);
+    (void)hipFree(c->mom2);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
     return MTS_OK;
@@ -511,6 +553,7 @@ int mts_destroy(mts_ctx *c) {
 int mts_init_fields(mts_ctx *c, uint64_t seed) {
     if (!c) return MTS_EINVAL;
     c->cur = 0;
+    c->mcur = 0;
     c->step_count = 0;
     c->meta.clear();
     c->produced = c->drained = 0;
@@ -781,6 +824,38 @@ int mts_bandwidth_probe(mts_ctx *c, int32_t reps, double *copy_gbps, double *pat
     return rc;
 }
 
+int mts_set_time_blocking(mts_ctx *c, int32_t steps, int32_t ty, int32_t tz) {
+    if (!c) return MTS_EINVAL;
+    if (steps == 1) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->tblock = 1;
+        return MTS_OK;
+    }
+    if (steps != 2) return fail(c, MTS_EINVAL, "time blocking: steps must be 1 or 2");
+    if (c->p.precision != MTS_FP32) return fail(c, MTS_EINVAL, "time blocking: FP32 only");
+    if (!pair_tile_supported(TileShape{ty, tz})) return fail(c, MTS_EINVAL, "time blocking: ty must be 3 or 7 and tz >= 1");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!c->mom2) {
+        hipError_t e = hipMalloc(&c->mom2, (size_t)10 * c->plane * c->esz);
+        if (e != hipSuccess) {
+            c->mom2 = nullptr;
+            (void)hipGetLastError();
+            return fail(c, MTS_ENOMEM, std::string("time blocking: second momentum copy: ") + hipGetErrorString(e));
+        }
+    }
+    c->tblock = 2;
+    c->tile2 = TileShape{ty, tz};
+    return MTS_OK;
+}
+
+int mts_get_time_blocking(const mts_ctx *c, int32_t *steps, int32_t *ty, int32_t *tz) {
+    if (!c || !steps || !ty || !tz) return MTS_EINVAL;
+    *steps = c->tblock;
+    *ty = c->tile2.ty;
+    *tz = c->tile2.tz;
+    return MTS_OK;
+}
+
 int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, double *ms_out) {
     if (!c || steps < 1) return MTS_EINVAL;
     const std::vector<int> tys = c->p.precision == MTS_FP64 ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 12};
@@ -791,6 +866,7 @@ int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, do
     const bool timing = c->timing;
     c->p.diag_every = 0;
     c->timing = false;
+    c->tblock = 1;               // single-step shapes first; the choice is set at the end
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = MTS_OK;
     auto hip = [&](hipError_t e, const char *what) {
@@ -824,17 +900,61 @@ int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, do
             }
         }
     }
-    c->nt = pick_nt;
+    // two steps per sweep (FP32), timed over an even number of steps, per step
+    double best_ps = best / steps;
+    int pick_tb = 1;
+    TileShape pick2 = c->tile2;
+    bool pick2_nt = pick_nt;
+    const int32_t steps2 = 2 * ((steps + 1) / 2);
+    if (rc == MTS_OK && c->p.precision == MTS_FP32) {
+        if (rc == MTS_OK) rc = mts_set_tile(c, pick.ty, pick.tz);
+        bool room = true;
+        for (int nt = 0; nt < 2 && rc == MTS_OK && room; nt++)
+            for (int ty : {3, 7})
+                for (int tz : tzs) {
+                    if (rc != MTS_OK || !room) break;
+                    if (tz > 2 * c->p.nz && tz != 8) continue;
+                    c->nt = nt != 0;
+                    const int r2 = mts_set_time_blocking(c, 2, ty, tz);
+                    if (r2 == MTS_ENOMEM) {   // no room for the second momentum copy: single steps only
+                        room = false;
+                        break;
+                    }
+                    if ((rc = r2) != MTS_OK) break;
+                    if ((rc = mts_step(c, 2, 1.0, 0.5, 1.0)) != MTS_OK) break;   // warm
+                    if (!hip(hipEventRecord(e0, c->stream), "hipEventRecord")) break;
+                    if ((rc = mts_step(c, steps2, 1.2, 0.5, 1.0)) != MTS_OK) break;
+                    float ms = 0;
+                    if (!(hip(hipEventRecord(e1, c->stream), "hipEventRecord") &&
+                          hip(hipEventSynchronize(e1), "hipEventSynchronize") &&
+                          hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime")))
+                        break;
+                    if (ms / steps2 < best_ps) {
+                        best_ps = ms / steps2;
+                        pick_tb = 2;
+                        pick2 = TileShape{ty, tz};
+                        pick2_nt = nt != 0;
+                    }
+                }
+        c->err.clear();
+    }
+    c->nt = pick_tb == 2 ? pick2_nt : pick_nt;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     c->p.diag_every = d;
     c->timing = timing;
     if (rc != MTS_OK) return rc;
     if ((rc = mts_set_tile(c, pick.ty, pick.tz)) != MTS_OK) return rc;
-    if ((rc = mts_init_fields(c, 0)) != MTS_OK) return rc;
+    if ((rc = mts_set_time_blocking(c, pick_tb, pick2.ty, pick2.tz)) != MTS_OK) return rc;
+    if ((rc = mts_init_fields(c, 0)) != MTS_OK) return rc;   // momenta back in the state buffer
+    if (pick_tb == 1 && c->mom2) {                           // the second momentum copy is not needed
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        (void)hipFree(c->mom2);
+        c->mom2 = nullptr;
+    }
     if (ty_out) *ty_out = pick.ty;
     if (tz_out) *tz_out = pick.tz;
-    if (ms_out) *ms_out = best / steps;
+    if (ms_out) *ms_out = best_ps;
     return MTS_OK;
 }
 
@@ -845,18 +965,21 @@ int mts_timing_enable(mts_ctx *c, int32_t on) {
 }
 
 int mts_timing_read(mts_ctx *c, int64_t *n_plain, double *ms_plain, int64_t *n_diag, double *ms_diag,
-                    double *ms_post) {
+                    double *ms_post, int64_t *n_pair, double *ms_pair) {
     if (!c) return MTS_EINVAL;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    int64_t np = 0, nd = 0;
-    double tp = 0, td = 0, tq = 0;
+    int64_t np = 0, nd = 0, n2 = 0;
+    double tp = 0, td = 0, tq = 0, t2 = 0;
     for (const auto &mk : c->marks) {
         float ms = 0;
         HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[mk.a], c->ev_pool[mk.b]));
         if (mk.kind == 0) np++, tp += ms;
         else if (mk.kind == 1) nd++, td += ms;
+        else if (mk.kind == 3) n2++, t2 += ms;
         else tq += ms;
     }
+    if (n_pair) *n_pair = n2;
+    if (ms_pair) *ms_pair = t2;
     c->marks.clear();
     c->ev_used = 0;
     if (n_plain) *n_plain = np;

@@ -11,18 +11,22 @@ namespace mts {
 
 template <typename T>
 __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+#pragma clang fp contract(off)
     return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
 template <typename T>
 __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {  // conj(a) * b
+#pragma clang fp contract(off)
     return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
 }
 template <typename T>
 __device__ __forceinline__ T imc(cx<T> a, cx<T> b) {  // Im(conj(a) * b)
+#pragma clang fp contract(off)
     return a.re * b.im - a.im * b.re;
 }
 template <typename T>
 __device__ __forceinline__ T norm2(cx<T> a) {
+#pragma clang fp contract(off)
     return a.re * a.re + a.im * a.im;
 }
 
@@ -81,12 +85,30 @@ __device__ __forceinline__ void st_stream(cx<T> *p, cx<T> v) {
     }
 }
 
+// XCD-contiguous numbering of a 1-D grid of nblk workgroups: the blocks the
+// hardware deals to XCD k (k, k + 8, ...) become one contiguous run, so
+// neighbouring tiles (which share halo rows) run under one L2.
+__device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t nblk) {
+    constexpr uint32_t NXCD = 8;
+    const uint32_t xcd = b % NXCD, slot = b / NXCD;
+    const uint32_t per = nblk / NXCD, extra = nblk % NXCD;
+    return xcd * per + min(xcd, extra) + slot;
+}
+
 // link phasor exp(-i h A)
 template <typename T>
 __device__ __forceinline__ cx<T> phasor(T hA) {
     T s, c;
     sincos_t(hA, &s, &c);
     return {c, -s};
+}
+// The same from h and A, the product rounded on its own (never fused into
+// the caller's arithmetic), so every kernel gets the same phasor bits.
+template <typename T>
+__device__ __forceinline__ cx<T> phasor(T h, T A) {
+#pragma clang fp contract(off)
+    const T hA = h * A;
+    return phasor<T>(hA);
 }
 
 // plaquette angle from its four links, in the order

@@ -109,6 +109,16 @@ hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> 
                             bool diag, Partials part, TileShape ts, T *alpha, uint32_t plane, bool nt,
                             hipStream_t st);
 
+// Two steps in one sweep (temporal blocking, FP32): reads fields n from
+// `in` and momenta n - 1/2 from `min_`, writes fields n + 2 to `out` and
+// momenta n + 3/2 to `mout` (all four distinct); c1, c2 are the
+// coefficients of steps n and n + 1.  A workgroup owns 64 x ts.ty sites
+// (ty in {3, 7}) over ts.tz planes.  FP64 returns hipErrorNotSupported.
+bool pair_tile_supported(TileShape ts);
+template <typename T>
+hipError_t launch_step_pair(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> min_, Moms<T> mout,
+                            const StepCoef<T> &c1, const StepCoef<T> &c2, TileShape ts, bool nt, hipStream_t st);
+
 // One box of an ensemble advanced by a single launch.
 template <typename T>
 struct BatchBox {

@@ -20,12 +20,12 @@
 // rows shared by neighbouring tiles inside one L2.
 #include "device.h"
 #include "kernels.h"
+#include "site.h"
 
 namespace mts {
 
 namespace {
 
-constexpr int NXCD = 8;
 constexpr int LW = 66;    // LDS row width: 64 + two halo columns
 
 __device__ __forceinline__ int wrapi(int v, int n) {
@@ -47,14 +47,6 @@ __device__ __forceinline__ cx<T> ldc(const Lds<T, TY> &L, int sec, int q, int i)
 }
 
 }  // namespace
-
-// XCD-contiguous numbering of a 1-D grid of nblk workgroups: the blocks the
-// hardware deals to XCD k (k, k + 8, ...) become one contiguous run.
-__device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t nblk) {
-    const uint32_t xcd = b % NXCD, slot = b / NXCD;
-    const uint32_t per = nblk / NXCD, extra = nblk % NXCD;
-    return xcd * per + min(xcd, extra) + slot;
-}
 
 // One tile (64 x TY columns, planes [Z0, Z0 + TZ)) of one box; accumulates the
 // integer-time sums of its interior sites into acc when DIAG.  With COOL the
@@ -117,7 +109,7 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
 #pragma unroll
         for (int sec = 0; sec < 2; sec++)
 #pragma unroll
-            for (int i = 0; i < 3; i++) U[sec][i] = phasor<T>(c.h * A[sec][i]);
+            for (int i = 0; i < 3; i++) U[sec][i] = phasor<T>(c.h, A[sec][i]);
     };
 
     load_plane(wrapi(zbeg - 1, g.nz), cf, cA, cU);
@@ -153,26 +145,13 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
         }
         __syncthreads();
 
-        // own plaquette phasors of plane z: P = U_i(x) U_j(x+i) conj(U_i(x+j)) conj(U_j(x))
+        // own plaquette phasors of plane z
         T sn[2][3], cs[2][3];
 #pragma unroll
         for (int sec = 0; sec < 2; sec++) {
-            const cx<T> uy_px = ldc(L, sec, Q_UYR, lxp), ux_py = ldc(L, sec, Q_UXR, lyp);
-            const cx<T> uz_px = ldc(L, sec, Q_UZR, lxp), uz_py = ldc(L, sec, Q_UZR, lyp);
-            const cx<T> ux = cU[sec][0], uy = cU[sec][1], uz = cU[sec][2];
-            // xy: U_x(x) U_y(x+x) conj(U_x(x+y) U_y(x))
-            const cx<T> axy = cmul(ux, uy_px), bxy = cmul(ux_py, uy);
-            const cx<T> Pxy = cmulc(bxy, axy);     // conj(b) a
-            const cx<T> axz = cmul(ux, uz_px), bxz = cmul(nU[sec][0], uz);
-            const cx<T> Pxz = cmulc(bxz, axz);
-            const cx<T> ayz = cmul(uy, uz_py), byz = cmul(nU[sec][1], uz);
-            const cx<T> Pyz = cmulc(byz, ayz);
-            sn[sec][0] = -Pxy.im;
-            sn[sec][1] = -Pxz.im;
-            sn[sec][2] = -Pyz.im;
-            cs[sec][0] = Pxy.re;
-            cs[sec][1] = Pxz.re;
-            cs[sec][2] = Pyz.re;
+            own_plaquettes(cU[sec][0], cU[sec][1], cU[sec][2], ldc(L, sec, Q_UYR, lxp), ldc(L, sec, Q_UXR, lyp),
+                           ldc(L, sec, Q_UZR, lxp), ldc(L, sec, Q_UZR, lyp), nU[sec][0], nU[sec][1], sn[sec],
+                           cs[sec]);
             if (owner) {
                 L.v[sec][Q_SXY][li] = sn[sec][0];
                 L.v[sec][Q_SXZ][li] = sn[sec][1];
@@ -185,77 +164,63 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
             T Kd = 0, Gd = 0, Kg = 0, Bg = 0, mod2[2] = {0, 0};
 #pragma unroll
             for (int sec = 0; sec < 2; sec++) {
-                const cx<T> f = cf[sec], o = cf[1 - sec];
-                const cx<T> fxp = ldc(L, sec, Q_FR, lxp), fxm = ldc(L, sec, Q_FR, lxm);
-                const cx<T> fyp = ldc(L, sec, Q_FR, lyp), fym = ldc(L, sec, Q_FR, lym);
-                const cx<T> fzp = nf[sec], fzm = pf[sec];
-                const cx<T> ux = cU[sec][0], uy = cU[sec][1], uz = cU[sec][2];
-                const cx<T> ux_m = ldc(L, sec, Q_UXR, lxm), uy_m = ldc(L, sec, Q_UYR, lym), uz_m = pUz[sec];
-                const cx<T> wx = cmul(ux, fxp), wy = cmul(uy, fyp), wz = cmul(uz, fzp);
-                const cx<T> vx = cmulc(ux_m, fxm), vy = cmulc(uy_m, fym), vz = cmulc(uz_m, fzm);
-
-                cx<T> lap;
-                lap.re = (((wx.re + vx.re) + (wy.re + vy.re)) + (wz.re + vz.re)) - T(6) * f.re;
-                lap.im = (((wx.im + vx.im) + (wy.im + vy.im)) + (wz.im + vz.im)) - T(6) * f.im;
-                const T m2 = norm2(f), o2 = norm2(o);
-                const T br = c.lamh[sec] * (m2 - c.sig2[sec]) - c.kap * (o2 - c.sig2[1 - sec]);
-                cx<T> F;
-                F.re = c.inv_h2 * lap.re - br * f.re;
-                F.im = c.inv_h2 * lap.im - br * f.im;
-
-                cx<T> p1;
-                if constexpr (COOL) {
-                    p1 = F;                 // phi flows along its force
-                } else {
-                    p1.re = c.cpi * p0[sec].re + c.kpi * F.re;
-                    p1.im = c.cpi * p0[sec].im + c.kpi * F.im;
-                    st_stream<NT>(&mom.pi[sec][s], p1);
+                SiteIn<T> q;
+                q.f = cf[sec];
+                q.o = cf[1 - sec];
+                q.fxp = ldc(L, sec, Q_FR, lxp);
+                q.fxm = ldc(L, sec, Q_FR, lxm);
+                q.fyp = ldc(L, sec, Q_FR, lyp);
+                q.fym = ldc(L, sec, Q_FR, lym);
+                q.fzp = nf[sec];
+                q.fzm = pf[sec];
+                q.ux = cU[sec][0];
+                q.uy = cU[sec][1];
+                q.uz = cU[sec][2];
+                q.ux_m = ldc(L, sec, Q_UXR, lxm);
+                q.uy_m = ldc(L, sec, Q_UYR, lym);
+                q.uz_m = pUz[sec];
+                q.sxy = sn[sec][0];
+                q.sxz = sn[sec][1];
+                q.syz = sn[sec][2];
+                q.sxy_my = L.v[sec][Q_SXY][lym];
+                q.sxy_mx = L.v[sec][Q_SXY][lxm];
+                q.sxz_mx = L.v[sec][Q_SXZ][lxm];
+                q.syz_my = L.v[sec][Q_SYZ][lym];
+                q.sxz_mz = psxz[sec];
+                q.syz_mz = psyz[sec];
+                if constexpr (!COOL) {
+                    q.p0 = p0[sec];
+#pragma unroll
+                    for (int i = 0; i < 3; i++) q.e0[i] = e0[sec][i];
                 }
-                cx<T> fn;
-                fn.re = f.re + c.k * p1.re;
-                fn.im = f.im + c.k * p1.im;
-                st_stream<NT>(&out.phi[sec][s], fn);
-
-                const T sxy = sn[sec][0], sxz = sn[sec][1], syz = sn[sec][2];
-                const T sxy_my = L.v[sec][Q_SXY][lym], sxy_mx = L.v[sec][Q_SXY][lxm];
-                const T sxz_mx = L.v[sec][Q_SXZ][lxm], syz_my = L.v[sec][Q_SYZ][lym];
-                const T sxz_mz = psxz[sec], syz_mz = psyz[sec];
-                const T Mx = -c.inv_h3 * ((sxy - sxy_my) + (sxz - sxz_mz));
-                const T My = -c.inv_h3 * ((sxy_mx - sxy) + (syz - syz_mz));
-                const T Mz = -c.inv_h3 * ((sxz_mx - sxz) + (syz_my - syz));
-                const T Jx = c.cur[sec] * imc(f, wx), Jy = c.cur[sec] * imc(f, wy), Jz = c.cur[sec] * imc(f, wz);
-                T e1x, e1y, e1z;
-                if constexpr (COOL) {
-                    e1x = Mx + Jx;          // the links flow along their force
-                    e1y = My + Jy;
-                    e1z = Mz + Jz;
-                } else {
-                    e1x = c.cE * e0[sec][0] + c.kE * (Mx + Jx);
-                    e1y = c.cE * e0[sec][1] + c.kE * (My + Jy);
-                    e1z = c.cE * e0[sec][2] + c.kE * (Mz + Jz);
-                    st_stream<NT>(&mom.E[sec][0][s], e1x);
-                    st_stream<NT>(&mom.E[sec][1][s], e1y);
-                    st_stream<NT>(&mom.E[sec][2][s], e1z);
+#pragma unroll
+                for (int i = 0; i < 3; i++) q.a[i] = cA[sec][i];
+                const SiteOut<T> r = site_update<T, COOL>(c, sec, q);
+                if constexpr (!COOL) {
+                    st_stream<NT>(&mom.pi[sec][s], r.p1);
+#pragma unroll
+                    for (int i = 0; i < 3; i++) st_stream<NT>(&mom.E[sec][i][s], r.e1[i]);
                 }
-                st_stream<NT>(&out.A[sec][0][s], cA[sec][0] + c.k * e1x);
-                st_stream<NT>(&out.A[sec][1][s], cA[sec][1] + c.k * e1y);
-                st_stream<NT>(&out.A[sec][2][s], cA[sec][2] + c.k * e1z);
+                st_stream<NT>(&out.phi[sec][s], r.fn);
+#pragma unroll
+                for (int i = 0; i < 3; i++) st_stream<NT>(&out.A[sec][i][s], r.an[i]);
 
                 if constexpr (DIAG) {
+                    const cx<T> f = cf[sec];
                     cx<T> pb;
-                    pb.re = T(0.5) * (p0[sec].re + p1.re);
-                    pb.im = T(0.5) * (p0[sec].im + p1.im);
+                    pb.re = T(0.5) * (p0[sec].re + r.p1.re);
+                    pb.im = T(0.5) * (p0[sec].im + r.p1.im);
                     Kd += norm2(pb);
                     cx<T> dx_, dy_, dz_;
-                    dx_.re = wx.re - f.re; dx_.im = wx.im - f.im;
-                    dy_.re = wy.re - f.re; dy_.im = wy.im - f.im;
-                    dz_.re = wz.re - f.re; dz_.im = wz.im - f.im;
+                    dx_.re = r.wx.re - f.re; dx_.im = r.wx.im - f.im;
+                    dy_.re = r.wy.re - f.re; dy_.im = r.wy.im - f.im;
+                    dz_.re = r.wz.re - f.re; dz_.im = r.wz.im - f.im;
                     Gd += c.inv_h2 * ((norm2(dx_) + norm2(dy_)) + norm2(dz_));
-                    const T ebx = T(0.5) * (e0[sec][0] + e1x), eby = T(0.5) * (e0[sec][1] + e1y),
-                            ebz = T(0.5) * (e0[sec][2] + e1z);
+                    const T ebx = T(0.5) * (e0[sec][0] + r.e1[0]), eby = T(0.5) * (e0[sec][1] + r.e1[1]),
+                            ebz = T(0.5) * (e0[sec][2] + r.e1[2]);
                     Kg += c.inv_2e2[sec] * ((ebx * ebx + eby * eby) + ebz * ebz);
                     Bg += c.inv_e2h4[sec] * (((T(1) - cs[sec][0]) + (T(1) - cs[sec][1])) + (T(1) - cs[sec][2]));
-                    mod2[sec] = m2;
+                    mod2[sec] = r.m2;
                 }
             }
             if constexpr (DIAG) {

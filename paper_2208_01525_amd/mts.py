@@ -19,7 +19,7 @@ MTS_FP32, MTS_FP64 = 1, 2
 
 EXPORTS = ("mts_state_bytes", "mts_create", "mts_destroy", "mts_init_fields", "mts_step", "mts_cool", "mts_diagnostics",
            "mts_get_fields", "mts_set_fields", "mts_get_windings", "mts_get_cells", "mts_get_sites", "mts_segments", "mts_set_tile", "mts_get_tile", "mts_set_streaming_stores", "mts_bandwidth_probe", "mts_get_streaming_stores", "mts_autotune", "mts_timing_enable",
-           "mts_timing_read", "mts_last_error", "mts_strerror",
+           "mts_timing_read", "mts_set_time_blocking", "mts_get_time_blocking", "mts_last_error", "mts_strerror",
            "mts_batch_state_bytes", "mts_batch_create", "mts_batch_destroy", "mts_batch_size",
            "mts_batch_init_fields", "mts_batch_step", "mts_batch_diagnostics", "mts_batch_get_fields",
            "mts_batch_set_fields", "mts_batch_set_tile", "mts_batch_set_streaming_stores", "mts_batch_get_streaming_stores", "mts_batch_timing_read", "mts_batch_autotune",
@@ -118,7 +118,9 @@ def load():
     L.mts_batch_autotune.argtypes = [vp, ctypes.c_int32, i32p, i32p, ctypes.POINTER(ctypes.c_double)]
     L.mts_timing_enable.argtypes = [vp, ctypes.c_int32]
     i64p, dp = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
-    L.mts_timing_read.argtypes = [vp, i64p, dp, i64p, dp, dp]
+    L.mts_timing_read.argtypes = [vp, i64p, dp, i64p, dp, dp, i64p, dp]
+    L.mts_set_time_blocking.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    L.mts_get_time_blocking.argtypes = [vp, i32p, i32p, i32p]
     L.mts_last_error.argtypes = [vp]
     L.mts_last_error.restype = ctypes.c_char_p
     L.mts_strerror.argtypes = [ctypes.c_int]
@@ -299,12 +301,20 @@ class Lattice:
         self._check(self.L.mts_timing_enable(self.ctx, 1 if on else 0))
 
     def timing_read(self):
-        n0, n1 = ctypes.c_int64(), ctypes.c_int64()
-        t0, t1, t2 = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        n0, n1, n2 = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        t0, t1, t2, t3 = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         self._check(self.L.mts_timing_read(self.ctx, ctypes.byref(n0), ctypes.byref(t0), ctypes.byref(n1),
-                                           ctypes.byref(t1), ctypes.byref(t2)))
+                                           ctypes.byref(t1), ctypes.byref(t2), ctypes.byref(n2), ctypes.byref(t3)))
         return {"n_plain": n0.value, "ms_plain": t0.value, "n_diag": n1.value, "ms_diag": t1.value,
-                "ms_post": t2.value}
+                "ms_post": t2.value, "n_pair": n2.value, "ms_pair": t3.value}
+
+    def set_time_blocking(self, steps, ty=7, tz=32):
+        self._check(self.L.mts_set_time_blocking(self.ctx, int(steps), int(ty), int(tz)))
+
+    def get_time_blocking(self):
+        n, ty, tz = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.L.mts_get_time_blocking(self.ctx, ctypes.byref(n), ctypes.byref(ty), ctypes.byref(tz)))
+        return n.value, ty.value, tz.value
 
 
 def _darr(values, n):

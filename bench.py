@@ -44,17 +44,17 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(n, precision, tile, nt):
+def measured_traffic(n, precision, tile, nt, pf):
     """HBM bytes per launch of the update kernel from the committed rocprofv3
     counter summary, if it was taken on this kernel source, tile shape, store
-    mode and workload; else None."""
+    mode, load pipeline and workload; else None."""
     if n != 512 or precision != "fp32" or not os.path.exists(TRAFFIC_FILE):
         return None
     lines = [l.strip() for l in open(TRAFFIC_FILE) if l.strip() and not l.startswith("#")]
     head = dict(l.split("=", 1) for l in lines if " " not in l and "=" in l)
     if head.get("source_sha256") != kernel_source_hash():
         return None
-    want = f"{tile[0]},{tile[1]},{int(nt)}"
+    want = f"{tile[0]},{tile[1]},{int(nt)},{int(pf)}"
     for l in lines:
         kv = dict(f.split("=", 1) for f in l.split() if "=" in f)
         if kv.get("config") == want:
@@ -63,7 +63,7 @@ def measured_traffic(n, precision, tile, nt):
 
 
 def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0.5, s=1.0, eta_ref=128.0, seed=1,
-            tile=None):
+            tile=None, time_blocking=None):
     params = P.make_params(n, precision=precision, eta_ref=eta_ref, diag_every=diag_every)
     lat = P.Lattice(params, device="cuda:0")
     tuned = None
@@ -71,8 +71,12 @@ def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0
         lat.set_tile(*tile[:2])
         if len(tile) > 2:
             lat.set_streaming_stores(bool(tile[2]))
+        if len(tile) > 3:
+            lat.set_prefetch(bool(tile[3]))
     else:
         tuned = lat.autotune(4)      # times every tile shape on this machine (leaves seed-0 fields)
+    if time_blocking is not None:
+        lat.set_time_blocking(*time_blocking)
     ceiling = lat.bandwidth_probe(5)  # this box's copy rate and the update pattern's rate (overwrites)
     lat.init_fields(seed)
     lat.step(warmup, eta0, era_m, s)
@@ -107,7 +111,8 @@ def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0
         "roofline": {"bound": "hbm", "kernel": kname, "steps_per_launch": per_launch,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(n, precision, lat.get_tile(), lat.get_streaming_stores())
+                     "traffic": measured_traffic(n, precision, lat.get_tile(), lat.get_streaming_stores(),
+                                                lat.get_prefetch())
                      if per_launch == 1 else None,
                      "algorithmic_bytes": BYTES_PER_SITE[precision] * sites,
                      "box_ceiling": {**{k: round(v, 1) for k, v in ceiling.items()},
@@ -115,6 +120,7 @@ def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0
         "pure_step_value": sites / (kern_ms * 1e-3),
         "tile": lat.get_tile(),
         "streaming_stores": lat.get_streaming_stores(),
+        "prefetch": lat.get_prefetch(),
         "time_blocking": {"steps_per_sweep": tblock[0], "tile": list(tblock[1:])},
         "autotune_ms_per_step": tuned[2] if tuned else None,
         "last_record": {k: recs[-1][k] for k in ("eta", "xi_W", "xi_lag", "v2_lag", "f_total", "gauss_rel")}
@@ -207,7 +213,10 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only time a plain copy (counter calibration)")
     ap.add_argument("--source-hash", action="store_true", help="print the update kernel's source hash")
     ap.add_argument("--tile", type=str, default=None,
-                    help="ty,tz[,nt] of the update kernel (0,1: per-site kernel; nt 1/0: streaming or plain stores)")
+                    help="ty,tz[,nt[,pf]] of the update kernel (0,1: per-site kernel; nt 1/0: streaming or plain "
+                         "stores; pf 1/0: deeper load pipeline or not)")
+    ap.add_argument("--time-blocking", type=str, default=None,
+                    help="steps,ty,tz: steps per sweep (1, or 2: the two-step kernel with 64 x ty x tz tiles), FP32 leg")
     args = ap.parse_args()
     if args.source_hash:
         print(kernel_source_hash())
@@ -226,7 +235,8 @@ def main():
         return
 
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
-    fp32 = run_box(P, torch, args.n, "fp32", args.warmup, args.steps, diag_every=10, tile=tile)
+    tblock = tuple(int(v) for v in args.time_blocking.split(",")) if args.time_blocking else None
+    fp32 = run_box(P, torch, args.n, "fp32", args.warmup, args.steps, diag_every=10, tile=tile, time_blocking=tblock)
     print(f"fp32: {fp32['value']:.4g} site-updates/s, kernel {fp32['kernel_ms']:.3f} ms, "
           f"{fp32['roofline']['frac']:.3f} of HBM peak", file=sys.stderr, flush=True)
     fp64 = run_box(P, torch, args.n, "fp64", args.warmup, args.fp64_steps, diag_every=10) if args.fp64_steps else None
@@ -262,6 +272,7 @@ def main():
         "pure_step_value": fp32["pure_step_value"],
         "tile": fp32["tile"],
         "streaming_stores": fp32["streaming_stores"],
+        "prefetch": fp32["prefetch"],
         "time_blocking": fp32["time_blocking"],
         "diag_step_kernel_ms": fp32["diag_step_kernel_ms"],
         "diag_post_ms": fp32["diag_post_ms"],

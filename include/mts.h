@@ -228,6 +228,14 @@ int mts_get_tile(const mts_ctx *ctx, int32_t *ty, int32_t *tz);
 int mts_set_streaming_stores(mts_ctx *ctx, int32_t on);
 int mts_get_streaming_stores(const mts_ctx *ctx, int32_t *on);
 
+/* Deeper load pipeline in the tiled update's plain steps: on (1) loads each
+ * plane's fields two planes before they are used (more registers per
+ * thread, fewer stalls on HBM); off (0, the default) one plane before.
+ * FP32 diagnostic steps always use it.  Results are bitwise
+ * identical; the autotuner tries both.  Synchronises the stream. */
+int mts_set_prefetch(mts_ctx *ctx, int32_t on);
+int mts_get_prefetch(const mts_ctx *ctx, int32_t *on);
+
 /* Temporal blocking (FP32): with steps = 2, every two consecutive plain
  * steps (no diagnostics due at either) run as one sweep of a two-level
  * tiled kernel (tiles of 64 x ty sites, ty in {3, 7}, tz >= 1 planes per
@@ -247,7 +255,8 @@ int mts_get_time_blocking(const mts_ctx *ctx, int32_t *steps, int32_t *ty, int32
  * (ty in {4, 8, 12} -- {4, 8} in FP64 -- by tz in {8, 16, 32, 64}, with and
  * without streaming stores) on this
  * box with HIP events, keep the fastest, and report it (and its ms per
- * step).  In FP32 it then times the two-step kernel (ty in {3, 7} by the
+ * step), each with and without the deeper load pipeline
+ * (mts_set_prefetch).  In FP32 it then times the two-step kernel (ty in {3, 7} by the
  * same tz and store modes, over an even number of steps) and switches
  * time blocking on if that is faster per step (mts_get_time_blocking tells
  * which; ms_per_step is the best of both).  The choice changes speed only:

@@ -41,6 +41,7 @@ struct mts_ctx {
     uint32_t *nblk_dev = nullptr;
     TileShape tile{8, 32};       // ty = 0: per-site kernel
     bool nt = true;              // streaming stores in the tiled update
+    bool pf = false;             // loads one plane ahead in the tiled update (plain steps)
     int tblock = 1;              // leapfrog steps per sweep through HBM (1, or 2: two-step kernel)
     TileShape tile2{7, 32};      // tile of the two-step kernel
     void *mom2 = nullptr;        // second momentum copy (10 planes), allocated for two-step sweeps
@@ -322,7 +323,7 @@ int do_step(mts_ctx *c, int32_t n, double eta, double era_m, double s) {
                                : launch_step_tile<T>(c->g, in, out, mom, coef, diag, part,
                                                      diag ? diag_tile(c) : c->tile,
                                                      static_cast<T *>(c->alpha), (uint32_t)c->plane, c->nt,
-                                                     c->stream);
+                                                     c->pf, c->stream);
             if (e != hipSuccess) return hipfail(c, e, "step kernel launch");
         }
         // the step is enqueued: the bookkeeping advances even if its diagnostics fail
@@ -771,6 +772,19 @@ int mts_set_streaming_stores(mts_ctx *c, int32_t on) {
     return MTS_OK;
 }
 
+int mts_set_prefetch(mts_ctx *c, int32_t on) {
+    if (!c) return MTS_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->pf = on != 0;
+    return MTS_OK;
+}
+
+int mts_get_prefetch(const mts_ctx *c, int32_t *on) {
+    if (!c || !on) return MTS_EINVAL;
+    *on = c->pf ? 1 : 0;
+    return MTS_OK;
+}
+
 int mts_get_streaming_stores(const mts_ctx *c, int32_t *on) {
     if (!c || !on) return MTS_EINVAL;
     *on = c->nt ? 1 : 0;
@@ -876,14 +890,16 @@ int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, do
     hip(hipEventCreate(&e0), "hipEventCreate") && hip(hipEventCreate(&e1), "hipEventCreate");
     double best = INFINITY;
     TileShape pick = c->tile;
-    bool pick_nt = c->nt;
+    bool pick_nt = c->nt, pick_pf = c->pf;
     if (rc == MTS_OK) rc = mts_init_fields(c, 0);
+    for (int pf = 0; pf < 2; pf++)
     for (int nt = 0; nt < 2; nt++)
     for (int ty : tys) {
         for (int tz : tzs) {
             if (rc != MTS_OK) break;
             if (tz > 2 * c->p.nz && tz != 8) continue;
             c->nt = nt != 0;
+            c->pf = pf != 0;
             if ((rc = mts_set_tile(c, ty, tz)) != MTS_OK) break;
             if ((rc = mts_step(c, 1, 1.0, 0.5, 1.0)) != MTS_OK) break;       // warm
             if (!hip(hipEventRecord(e0, c->stream), "hipEventRecord")) break;
@@ -897,6 +913,7 @@ int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, do
                 best = ms;
                 pick = TileShape{ty, tz};
                 pick_nt = nt != 0;
+                pick_pf = pf != 0;
             }
         }
     }
@@ -939,6 +956,7 @@ int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, do
         c->err.clear();
     }
     c->nt = pick_tb == 2 ? pick2_nt : pick_nt;
+    c->pf = pick_pf;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     c->p.diag_every = d;

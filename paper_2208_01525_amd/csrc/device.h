@@ -9,25 +9,30 @@
 
 namespace mts {
 
+// Complex products with their fused multiply-adds written out (and no other
+// contraction), so every kernel that uses them rounds identically.
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T>
 __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
 #pragma clang fp contract(off)
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return {fma_t(a.re, b.re, -(a.im * b.im)), fma_t(a.re, b.im, a.im * b.re)};
 }
 template <typename T>
 __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {  // conj(a) * b
 #pragma clang fp contract(off)
-    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+    return {fma_t(a.re, b.re, a.im * b.im), fma_t(a.re, b.im, -(a.im * b.re))};
 }
 template <typename T>
 __device__ __forceinline__ T imc(cx<T> a, cx<T> b) {  // Im(conj(a) * b)
 #pragma clang fp contract(off)
-    return a.re * b.im - a.im * b.re;
+    return fma_t(a.re, b.im, -(a.im * b.re));
 }
 template <typename T>
 __device__ __forceinline__ T norm2(cx<T> a) {
 #pragma clang fp contract(off)
-    return a.re * a.re + a.im * a.im;
+    return fma_t(a.re, a.re, a.im * a.im);
 }
 
 __device__ __forceinline__ void sincos_t(float x, float *s, float *c) { sincosf(x, s, c); }

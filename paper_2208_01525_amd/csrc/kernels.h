@@ -103,10 +103,11 @@ template <typename T>
 hipError_t launch_cool_tile(const Geom &g, Fields<T> in, Fields<T> out, const StepCoef<T> &c, TileShape ts,
                             hipStream_t st);
 
-// nt selects streaming (non-temporal) stores for the outputs.
+// nt selects streaming (non-temporal) stores for the outputs; pf loads the
+// fields of plain steps one plane further ahead (FP32 diagnostic steps always do).
 template <typename T>
 hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, const StepCoef<T> &c,
-                            bool diag, Partials part, TileShape ts, T *alpha, uint32_t plane, bool nt,
+                            bool diag, Partials part, TileShape ts, T *alpha, uint32_t plane, bool nt, bool pf,
                             hipStream_t st);
 
 // Two steps in one sweep (temporal blocking, FP32): reads fields n from

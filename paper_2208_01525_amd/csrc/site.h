@@ -1,8 +1,9 @@
 // site.h -- the per-site arithmetic of one leapfrog step (Correia & Martins,
 // arXiv:2208.01525, Sec. III: the Pi/Psi kick, the E/H kick and the drift),
 // shared by the single-step and the two-step tiled kernels so that both
-// evaluate every site with the same operations in the same order (their
-// results are bitwise identical).
+// evaluate every site with the same operations in the same order.  The fused
+// multiply-adds are written out and no other contraction is allowed, so the
+// two kernels' results are bitwise identical.
 #pragma once
 #include "device.h"
 
@@ -71,22 +72,22 @@ __device__ __forceinline__ SiteOut<T> site_update(const StepCoef<T> &c, int sec,
     r.wz = cmul(q.uz, q.fzp);
     const cx<T> vx = cmulc(q.ux_m, q.fxm), vy = cmulc(q.uy_m, q.fym), vz = cmulc(q.uz_m, q.fzm);
     cx<T> lap;
-    lap.re = (((r.wx.re + vx.re) + (r.wy.re + vy.re)) + (r.wz.re + vz.re)) - T(6) * f.re;
-    lap.im = (((r.wx.im + vx.im) + (r.wy.im + vy.im)) + (r.wz.im + vz.im)) - T(6) * f.im;
+    lap.re = fma_t(T(-6), f.re, ((r.wx.re + vx.re) + (r.wy.re + vy.re)) + (r.wz.re + vz.re));
+    lap.im = fma_t(T(-6), f.im, ((r.wx.im + vx.im) + (r.wy.im + vy.im)) + (r.wz.im + vz.im));
     r.m2 = norm2(f);
     const T o2 = norm2(q.o);
-    const T br = c.lamh[sec] * (r.m2 - c.sig2[sec]) - c.kap * (o2 - c.sig2[1 - sec]);
+    const T br = fma_t(c.lamh[sec], r.m2 - c.sig2[sec], -(c.kap * (o2 - c.sig2[1 - sec])));
     cx<T> F;
-    F.re = c.inv_h2 * lap.re - br * f.re;
-    F.im = c.inv_h2 * lap.im - br * f.im;
+    F.re = fma_t(c.inv_h2, lap.re, -(br * f.re));
+    F.im = fma_t(c.inv_h2, lap.im, -(br * f.im));
     if constexpr (COOL) {
         r.p1 = F;
     } else {
-        r.p1.re = c.cpi * q.p0.re + c.kpi * F.re;
-        r.p1.im = c.cpi * q.p0.im + c.kpi * F.im;
+        r.p1.re = fma_t(c.cpi, q.p0.re, c.kpi * F.re);
+        r.p1.im = fma_t(c.cpi, q.p0.im, c.kpi * F.im);
     }
-    r.fn.re = f.re + c.k * r.p1.re;
-    r.fn.im = f.im + c.k * r.p1.im;
+    r.fn.re = fma_t(c.k, r.p1.re, f.re);
+    r.fn.im = fma_t(c.k, r.p1.im, f.im);
 
     const T Mx = -c.inv_h3 * ((q.sxy - q.sxy_my) + (q.sxz - q.sxz_mz));
     const T My = -c.inv_h3 * ((q.sxy_mx - q.sxy) + (q.syz - q.syz_mz));
@@ -97,12 +98,12 @@ __device__ __forceinline__ SiteOut<T> site_update(const StepCoef<T> &c, int sec,
         r.e1[1] = My + Jy;
         r.e1[2] = Mz + Jz;
     } else {
-        r.e1[0] = c.cE * q.e0[0] + c.kE * (Mx + Jx);
-        r.e1[1] = c.cE * q.e0[1] + c.kE * (My + Jy);
-        r.e1[2] = c.cE * q.e0[2] + c.kE * (Mz + Jz);
+        r.e1[0] = fma_t(c.cE, q.e0[0], c.kE * (Mx + Jx));
+        r.e1[1] = fma_t(c.cE, q.e0[1], c.kE * (My + Jy));
+        r.e1[2] = fma_t(c.cE, q.e0[2], c.kE * (Mz + Jz));
     }
 #pragma unroll
-    for (int i = 0; i < 3; i++) r.an[i] = q.a[i] + c.k * r.e1[i];
+    for (int i = 0; i < 3; i++) r.an[i] = fma_t(c.k, r.e1[i], q.a[i]);
     return r;
 }
 

@@ -259,23 +259,25 @@ def test_small_workload_full_run(precision):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_tile_shapes_bitwise_identical(precision):
-    """Every tile shape of the z-marching kernel, with streaming or plain stores,
-    gives the same fields bit for bit (on a box with ragged tiles in every
-    direction)."""
+    """Every tile shape of the z-marching kernel, with streaming or plain stores and
+    with or without the deeper load pipeline, gives the same fields bit for bit (on
+    a box with ragged tiles in every direction)."""
     nx, ny, nz = 70, 21, 13
     st = rounded(I.random_full(nx, ny, nz, 11, link=0.5, mom=0.5), precision)
     ref = None
-    for ty, tz, nt in ((8, 32, True), (4, 1, False), (12, 5, True), (4, 7, True), (8, 13, False), (8, 32, False)):
+    for ty, tz, nt, pf in ((8, 32, True, False), (4, 1, False, False), (12, 5, True, True), (4, 7, True, True),
+                           (8, 13, False, True), (8, 32, False, False), (12, 64, True, True), (8, 2, True, True)):
         lat = lattice(nx, ny, nz, precision, eta_ref=9.0, diag_every=4)
         lat.set_tile(ty, tz)
         lat.set_streaming_stores(nt)
+        lat.set_prefetch(pf)
         lat.set_fields(st)
         lat.step(12, 1.0, 0.5, 1.0)
         got = lat.get_fields()
         recs = lat.diagnostics()
         if ref is None:
             ref, rrec = got, recs
-        assert np.array_equal(got, ref), (ty, tz, nt)
+        assert np.array_equal(got, ref), (ty, tz, nt, pf)
         for a, b in zip(recs, rrec):
             assert a["sum_energy"] == pytest.approx(b["sum_energy"], rel=1e-13)
             assert a["wind_abs"] == b["wind_abs"] and a["pq_count2"] == b["pq_count2"]

@@ -8,7 +8,8 @@
 //   level 0  the fields at n on a (TY+4) x 68 region (two halo rows and
 //            columns on each side), read from HBM;
 //   level 1  step n on the (TY+2) x 66 region inside it (momenta n - 1/2
-//            read from HBM); its fields and momenta stay in registers;
+//            read from HBM); its fields stay in registers, its momenta in a
+//            per-thread LDS ring;
 //   level 2  step n+1 on the 64 x TY interior, one plane behind level 1;
 //            fields n+2 and momenta n+3/2 are written to HBM.
 // Waves 0..TY+3 hold the rows of the region (lanes -> columns 2..65), wave

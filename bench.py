@@ -181,8 +181,20 @@ def cpu_baseline():
     t0 = time.perf_counter()
     O.run(m, st, steps, 1.0, 0.5, 1.0, diag_every=10)
     dt = time.perf_counter() - t0
-    return {"value": n ** 3 * steps / dt, "unit": "site-updates/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{n}^3 box, {steps} steps from eta=1 (m=1/2, s=1, diagnostics every 10), FP64, {dt:.1f} s"}
+    threads = O.num_threads()
+    # the same on one thread, on a smaller sample (about 3 s)
+    n1, steps1 = 64, 10
+    m1 = O.model(n1, eta_ref=128.0)
+    st1 = O.init_random_phase(m1, 1)
+    O.set_num_threads(1)
+    t1 = time.perf_counter()
+    O.run(m1, st1, steps1, 1.0, 0.5, 1.0, diag_every=10)
+    dt1 = time.perf_counter() - t1
+    O.set_num_threads(threads)
+    return {"value": n ** 3 * steps / dt, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n}^3 box, {steps} steps from eta=1 (m=1/2, s=1, diagnostics every 10), FP64, {dt:.1f} s",
+            "single_thread": {"value": n1 ** 3 * steps1 / dt1, "unit": "site-updates/s", "cores": 1,
+                              "sample": f"{n1}^3 box, {steps1} steps from eta=1 (same schedule), FP64, {dt1:.1f} s"}}
 
 
 def copy_probe(torch, gib=2, reps=5):

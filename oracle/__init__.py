@@ -89,6 +89,7 @@ def lib():
                               ctypes.c_int64, ctypes.c_int, ctypes.POINTER(Diag), ctypes.c_int]
         L.orc_run.restype = ctypes.c_int
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         _LIB = L
     return _LIB
 
@@ -221,6 +222,11 @@ def robust(m, sizes, min_length):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    """Threads the oracle uses from now on (results do not depend on it)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def derive(m, rec, mu=2.0 * math.pi):

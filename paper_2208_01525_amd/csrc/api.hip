@@ -241,19 +241,26 @@ struct TimedRegion {
 };
 
 // Diagnostic steps use the DIAG variant of the update kernel, which needs
-// more registers: it runs with at most 8 (FP32) or 4 (FP64) rows per tile so
-// that it never spills.  Tile shapes do not change results (bitwise).
+// more registers: in FP32 it runs with at most 8 rows per tile so that it
+// never spills.  Tile shapes do not change results (bitwise).
 TileShape diag_tile(const mts_ctx *c) {
     if (c->tile.ty == 0) return c->tile;
     const int cap = c->p.precision == MTS_FP64 ? 4 : 8;
     return TileShape{std::min(c->tile.ty, cap), c->tile.tz};
 }
 
+// FP64 diagnostic steps run the one-thread-per-site kernel: the tiled DIAG
+// variant in double needs about 300 registers a thread and spills 60-90 of
+// them (512^3: 28.7 ms per diagnostic step against 22.5 ms per site, plus
+// 1.1 ms for the separate phase kernel).
+// Ensembles do the same for their FP64 diagnostic steps (one launch per box).
+bool diag_per_site(const mts_ctx *c) { return c->tile.ty == 0 || c->p.precision == MTS_FP64; }
+
 // Partials per slot: the update kernel's blocks for the integer-time sums,
 // the per-site grid for the post-step diagnostic kernels.
 hipError_t upload_nblk(mts_ctx *c) {
     uint32_t nb[NSLOT];
-    const uint32_t step_blocks = c->tile.ty == 0 ? site_blocks(c->g) : tile_blocks(c->g, diag_tile(c));
+    const uint32_t step_blocks = diag_per_site(c) ? site_blocks(c->g) : tile_blocks(c->g, diag_tile(c));
     for (int q = 0; q < NSLOT; q++)
         nb[q] = q <= SL_GV ? step_blocks : (q <= SL_WIND_Q ? wind_blocks(c->g) : (q <= SL_OV_Q ? overlap_blocks(c->g) : 0));
     return hipMemcpy(c->nblk_dev, nb, sizeof(nb), hipMemcpyHostToDevice);
@@ -318,7 +325,7 @@ int do_step(mts_ctx *c, int32_t n, double eta, double era_m, double s) {
         Fields<T> in = fields_of<T>(c, c->cur), out = fields_of<T>(c, 1 - c->cur);
         {
             TimedRegion tr(c, diag ? 1 : 0);
-            hipError_t e = c->tile.ty == 0
+            hipError_t e = (c->tile.ty == 0 || (diag && diag_per_site(c)))
                                ? launch_step<T>(c->g, in, out, mom, coef, diag, part, c->stream)
                                : launch_step_tile<T>(c->g, in, out, mom, coef, diag, part,
                                                      diag ? diag_tile(c) : c->tile,
@@ -330,7 +337,7 @@ int do_step(mts_ctx *c, int32_t n, double eta, double era_m, double s) {
         hipError_t ep = hipSuccess;
         if (diag) {
             TimedRegion tr(c, 2);
-            ep = enqueue_diag_post<T>(c, b, eta_j, s, c->stream, c->tile.ty != 0);
+            ep = enqueue_diag_post<T>(c, b, eta_j, s, c->stream, !diag_per_site(c));
         }
         c->cur = 1 - c->cur;
         c->step_count++;
@@ -1196,14 +1203,23 @@ int batch_step_t(mts_batch *b, int32_t n, const double *eta0, const double *era_
     for (int32_t j = 0; j < n && err == hipSuccess; j++) {
         mts_ctx *c0 = b->box[0];
         const bool diag = d > 0 && (c0->step_count % d) == 0;
-        err = launch_step_tile_batch<T>(static_cast<const BatchBox<T> *>(diag ? b->boxes_diag_dev : b->boxes_dev),
-                                        (int)nbox, diag ? b->nblk_diag : b->nblk, c0->cur,
-                                        static_cast<const StepCoef<T> *>(b->coef_dev) + (size_t)j * nbox, diag,
-                                        diag ? b->ty_diag : b->ty, b->nt, b->stream);
+        if (diag && diag_per_site(c0)) {
+            // FP64 diagnostic steps: the per-site kernel, box by box (as single contexts do)
+            for (size_t k = 0; k < nbox && err == hipSuccess; k++) {
+                mts_ctx *c = b->box[k];
+                err = launch_step<T>(c->g, fields_of<T>(c, c->cur), fields_of<T>(c, 1 - c->cur), moms_of<T>(c),
+                                     tab[(size_t)j * nbox + k], true, Partials{c->partials, c->maxblk}, b->stream);
+            }
+        } else {
+            err = launch_step_tile_batch<T>(static_cast<const BatchBox<T> *>(diag ? b->boxes_diag_dev : b->boxes_dev),
+                                            (int)nbox, diag ? b->nblk_diag : b->nblk, c0->cur,
+                                            static_cast<const StepCoef<T> *>(b->coef_dev) + (size_t)j * nbox, diag,
+                                            diag ? b->ty_diag : b->ty, b->nt, b->stream);
+        }
         if (diag)
             for (size_t k = 0; k < nbox && err == hipSuccess; k++)
                 err = enqueue_diag_post<T>(b->box[k], books[k][j], eta0[k] + j * b->box[k]->p.dt, svals[k][j],
-                                           b->stream, true);
+                                           b->stream, !diag_per_site(b->box[k]));
         for (mts_ctx *c : b->box) {
             c->cur = 1 - c->cur;
             c->step_count++;

@@ -73,7 +73,47 @@ __device__ __forceinline__ void sincos_t(float x, float *s, float *c) {
     *s = sv;
     *c = cv;
 }
-__device__ __forceinline__ void sincos_t(double x, double *s, double *c) { sincos(x, s, c); }
+// The same in FP64: three-part split of pi/2 (to 160 bits), then the Taylor
+// series of sin to x^15 and cos to x^16 on [-pi/4, pi/4] (truncation below
+// 1e-16); within 1 ulp for |x| < 1e5 in an exact-arithmetic emulation.
+__device__ __forceinline__ void sincos_t(double x, double *s, double *c) {
+#pragma clang fp contract(off)
+    if (!(fabs(x) < 1.0e5)) {
+        sincos(x, s, c);
+        return;
+    }
+    constexpr double TWO_OVER_PI = 0.6366197723675814;
+    constexpr double C1 = 1.5707963267948966;        // fl(pi/2)
+    constexpr double C2 = 6.123233995736766e-17;     // fl(pi/2 - C1)
+    constexpr double C3 = -1.4973849048591698e-33;   // fl(pi/2 - C1 - C2)
+    const double j = rint(x * TWO_OVER_PI);
+    const int q = (int)j;
+    double r = __builtin_fma(-j, C1, x);
+    r = __builtin_fma(-j, C2, r);
+    r = __builtin_fma(-j, C3, r);
+    const double r2 = r * r;
+    // sin r = r + r^3 (-1/3! + r^2 (1/5! - ...)), cos r = 1 - r^2/2 + r^4 (1/4! - r^2 (1/6! - ...))
+    double ps = __builtin_fma(r2, -7.647163731819816e-13, 1.6059043836821613e-10);
+    ps = __builtin_fma(r2, ps, -2.505210838544172e-08);
+    ps = __builtin_fma(r2, ps, 2.7557319223985893e-06);
+    ps = __builtin_fma(r2, ps, -0.0001984126984126984);
+    ps = __builtin_fma(r2, ps, 0.008333333333333333);
+    ps = __builtin_fma(r2, ps, -0.16666666666666666);
+    const double sr = __builtin_fma(r2 * r, ps, r);
+    double pc = __builtin_fma(r2, 4.779477332387385e-14, -1.1470745597729725e-11);
+    pc = __builtin_fma(r2, pc, 2.08767569878681e-09);
+    pc = __builtin_fma(r2, pc, -2.755731922398589e-07);
+    pc = __builtin_fma(r2, pc, 2.48015873015873e-05);
+    pc = __builtin_fma(r2, pc, -0.001388888888888889);
+    pc = __builtin_fma(r2, pc, 0.041666666666666664);
+    const double cr = __builtin_fma(r2 * r2, pc, __builtin_fma(r2, -0.5, 1.0));
+    const bool swap = (q & 1) != 0;
+    double sv = swap ? cr : sr, cv = swap ? sr : cr;
+    if (q & 2) sv = -sv;
+    if ((q + 1) & 2) cv = -cv;
+    *s = sv;
+    *c = cv;
+}
 __device__ __forceinline__ float sin_t(float x) { return sinf(x); }
 __device__ __forceinline__ float cos_t(float x) { return cosf(x); }
 __device__ __forceinline__ double cos_t(double x) { return cos(x); }

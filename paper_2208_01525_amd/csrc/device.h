@@ -114,10 +114,22 @@ __device__ __forceinline__ void sincos_t(double x, double *s, double *c) {
     *s = sv;
     *c = cv;
 }
-__device__ __forceinline__ float sin_t(float x) { return sinf(x); }
-__device__ __forceinline__ float cos_t(float x) { return cosf(x); }
-__device__ __forceinline__ double cos_t(double x) { return cos(x); }
-__device__ __forceinline__ double sin_t(double x) { return sin(x); }
+
+// sin and cos alone, through the same reduction and polynomials (the
+// compiler shares the work where both are taken of one angle)
+template <typename T>
+__device__ __forceinline__ T sin_t(T x) {
+    T s, c;
+    sincos_t(x, &s, &c);
+    return s;
+}
+template <typename T>
+__device__ __forceinline__ T cos_t(T x) {
+    T s, c;
+    sincos_t(x, &s, &c);
+    return c;
+}
+
 __device__ __forceinline__ float atan2_t(float y, float x) { return atan2f(y, x); }
 __device__ __forceinline__ double atan2_t(double y, double x) { return atan2(y, x); }
 __device__ __forceinline__ float rint_t(float x) { return rintf(x); }

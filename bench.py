@@ -44,7 +44,7 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(n, precision, tile, nt, pf):
+def measured_traffic(n, precision, tile, nt, pf, pp=False):
     """HBM bytes per launch of the update kernel from the committed rocprofv3
     counter summary, if it was taken on this kernel source, tile shape, store
     mode, load pipeline and workload; else None."""
@@ -54,7 +54,7 @@ def measured_traffic(n, precision, tile, nt, pf):
     head = dict(l.split("=", 1) for l in lines if " " not in l and "=" in l)
     if head.get("source_sha256") != kernel_source_hash():
         return None
-    want = f"{tile[0]},{tile[1]},{int(nt)},{int(pf)}"
+    want = f"{tile[0]},{tile[1]},{int(nt)},{int(pf)}" + (",1" if pp else "")
     for l in lines:
         kv = dict(f.split("=", 1) for f in l.split() if "=" in f)
         if kv.get("config") == want:
@@ -73,6 +73,8 @@ def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0
             lat.set_streaming_stores(bool(tile[2]))
         if len(tile) > 3:
             lat.set_prefetch(bool(tile[3]))
+        if len(tile) > 4:
+            lat.set_momentum_pingpong(bool(tile[4]))
     else:
         tuned = lat.autotune(4)      # times every tile shape on this machine (leaves seed-0 fields)
     if time_blocking is not None:
@@ -112,7 +114,7 @@ def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(n, precision, lat.get_tile(), lat.get_streaming_stores(),
-                                                lat.get_prefetch())
+                                                lat.get_prefetch(), lat.get_momentum_pingpong())
                      if per_launch == 1 else None,
                      "algorithmic_bytes": BYTES_PER_SITE[precision] * sites,
                      "box_ceiling": {**{k: round(v, 1) for k, v in ceiling.items()},
@@ -121,6 +123,7 @@ def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0
         "tile": lat.get_tile(),
         "streaming_stores": lat.get_streaming_stores(),
         "prefetch": lat.get_prefetch(),
+        "momentum_pingpong": lat.get_momentum_pingpong(),
         "time_blocking": {"steps_per_sweep": tblock[0], "tile": list(tblock[1:])},
         "autotune_ms_per_step": tuned[2] if tuned else None,
         "last_record": {k: recs[-1][k] for k in ("eta", "xi_W", "xi_lag", "v2_lag", "f_total", "gauss_rel")}
@@ -225,8 +228,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only time a plain copy (counter calibration)")
     ap.add_argument("--source-hash", action="store_true", help="print the update kernel's source hash")
     ap.add_argument("--tile", type=str, default=None,
-                    help="ty,tz[,nt[,pf]] of the update kernel (0,1: per-site kernel; nt 1/0: streaming or plain "
-                         "stores; pf 1/0: deeper load pipeline or not)")
+                    help="ty,tz[,nt[,pf[,pp]]] of the update kernel (0,1: per-site kernel; nt 1/0: streaming or "
+                         "plain stores; pf 1/0: deeper load pipeline or not; pp 1/0: momentum ping-pong)")
     ap.add_argument("--time-blocking", type=str, default=None,
                     help="steps,ty,tz: steps per sweep (1, or 2: the two-step kernel with 64 x ty x tz tiles), FP32 leg")
     args = ap.parse_args()
@@ -285,6 +288,7 @@ def main():
         "tile": fp32["tile"],
         "streaming_stores": fp32["streaming_stores"],
         "prefetch": fp32["prefetch"],
+        "momentum_pingpong": fp32["momentum_pingpong"],
         "time_blocking": fp32["time_blocking"],
         "diag_step_kernel_ms": fp32["diag_step_kernel_ms"],
         "diag_post_ms": fp32["diag_post_ms"],

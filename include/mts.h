@@ -228,6 +228,17 @@ int mts_get_tile(const mts_ctx *ctx, int32_t *ty, int32_t *tz);
 int mts_set_streaming_stores(mts_ctx *ctx, int32_t on);
 int mts_get_streaming_stores(const mts_ctx *ctx, int32_t *on);
 
+/* Momentum ping-pong: with on = 1 the tiled kernel reads the momenta from
+ * one copy and writes them to the other (the state buffer's and a second
+ * copy the library allocates on first use, 40 bytes per site in FP32, 80 in
+ * FP64, freed by mts_destroy) instead of rewriting them in place, which HBM
+ * serves a few per cent faster; MTS_ENOMEM if the copy does not fit.
+ * Results are bitwise identical; steps on the per-site kernel stay in
+ * place.  on = 0 (the default) rewrites in place.  The autotuner tries it.
+ * Synchronises the stream.  Update of Sec. III. */
+int mts_set_momentum_pingpong(mts_ctx *ctx, int32_t on);
+int mts_get_momentum_pingpong(const mts_ctx *ctx, int32_t *on);
+
 /* Deeper load pipeline in the tiled update's plain steps: on (1) loads each
  * plane's fields two planes before they are used (more registers per
  * thread, fewer stalls on HBM); off (0, the default) one plane before.
@@ -256,7 +267,8 @@ int mts_get_time_blocking(const mts_ctx *ctx, int32_t *steps, int32_t *ty, int32
  * without streaming stores) on this
  * box with HIP events, keep the fastest, and report it (and its ms per
  * step), each with and without the deeper load pipeline
- * (mts_set_prefetch).  In FP32 it then times the two-step kernel (ty in {3, 7} by the
+ * (mts_set_prefetch), and the fastest of them with momentum ping-pong.
+ * In FP32 it then times the two-step kernel (ty in {3, 7} by the
  * same tz and store modes, over an even number of steps) and switches
  * time blocking on if that is faster per step (mts_get_time_blocking tells
  * which; ms_per_step is the best of both).  The choice changes speed only:

@@ -42,6 +42,7 @@ struct mts_ctx {
     TileShape tile{8, 32};       // ty = 0: per-site kernel
     bool nt = true;              // streaming stores in the tiled update
     bool pf = false;             // loads one plane ahead in the tiled update (plain steps)
+    bool mpp = false;            // tiled steps write the momenta to the other momentum copy
     int tblock = 1;              // leapfrog steps per sweep through HBM (1, or 2: two-step kernel)
     TileShape tile2{7, 32};      // tile of the two-step kernel
     void *mom2 = nullptr;        // second momentum copy (10 planes), allocated for two-step sweeps
@@ -323,16 +324,20 @@ int do_step(mts_ctx *c, int32_t n, double eta, double era_m, double s) {
         }
         Moms<T> mom = moms_of<T>(c);
         Fields<T> in = fields_of<T>(c, c->cur), out = fields_of<T>(c, 1 - c->cur);
+        const bool per_site = c->tile.ty == 0 || (diag && diag_per_site(c));
+        const bool pp = c->mpp && !per_site;   // momenta to the other copy (the per-site kernel works in place)
+        const Moms<T> mom_out = pp ? moms_at<T>(c, 1 - c->mcur) : mom;
         {
             TimedRegion tr(c, diag ? 1 : 0);
-            hipError_t e = (c->tile.ty == 0 || (diag && diag_per_site(c)))
+            hipError_t e = per_site
                                ? launch_step<T>(c->g, in, out, mom, coef, diag, part, c->stream)
-                               : launch_step_tile<T>(c->g, in, out, mom, coef, diag, part,
+                               : launch_step_tile<T>(c->g, in, out, mom, mom_out, coef, diag, part,
                                                      diag ? diag_tile(c) : c->tile,
                                                      static_cast<T *>(c->alpha), (uint32_t)c->plane, c->nt,
                                                      c->pf, c->stream);
             if (e != hipSuccess) return hipfail(c, e, "step kernel launch");
         }
+        if (pp) c->mcur = 1 - c->mcur;   // the diagnostic kernels below read the new momenta
         // the step is enqueued: the bookkeeping advances even if its diagnostics fail
         hipError_t ep = hipSuccess;
         if (diag) {
@@ -779,6 +784,35 @@ int mts_set_streaming_stores(mts_ctx *c, int32_t on) {
     return MTS_OK;
 }
 
+// The second momentum copy (10 planes), allocated on first use.
+int ensure_mom2(mts_ctx *c, const char *what) {
+    if (c->mom2) return MTS_OK;
+    hipError_t e = hipMalloc(&c->mom2, (size_t)10 * c->plane * c->esz);
+    if (e != hipSuccess) {
+        c->mom2 = nullptr;
+        (void)hipGetLastError();
+        return fail(c, MTS_ENOMEM, std::string(what) + ": second momentum copy: " + hipGetErrorString(e));
+    }
+    return MTS_OK;
+}
+
+int mts_set_momentum_pingpong(mts_ctx *c, int32_t on) {
+    if (!c) return MTS_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (on) {
+        const int rc = ensure_mom2(c, "momentum ping-pong");
+        if (rc != MTS_OK) return rc;
+    }
+    c->mpp = on != 0;
+    return MTS_OK;
+}
+
+int mts_get_momentum_pingpong(const mts_ctx *c, int32_t *on) {
+    if (!c || !on) return MTS_EINVAL;
+    *on = c->mpp ? 1 : 0;
+    return MTS_OK;
+}
+
 int mts_set_prefetch(mts_ctx *c, int32_t on) {
     if (!c) return MTS_EINVAL;
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -856,14 +890,8 @@ int mts_set_time_blocking(mts_ctx *c, int32_t steps, int32_t ty, int32_t tz) {
     if (c->p.precision != MTS_FP32) return fail(c, MTS_EINVAL, "time blocking: FP32 only");
     if (!pair_tile_supported(TileShape{ty, tz})) return fail(c, MTS_EINVAL, "time blocking: ty must be 3 or 7 and tz >= 1");
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (!c->mom2) {
-        hipError_t e = hipMalloc(&c->mom2, (size_t)10 * c->plane * c->esz);
-        if (e != hipSuccess) {
-            c->mom2 = nullptr;
-            (void)hipGetLastError();
-            return fail(c, MTS_ENOMEM, std::string("time blocking: second momentum copy: ") + hipGetErrorString(e));
-        }
-    }
+    const int rc = ensure_mom2(c, "time blocking");
+    if (rc != MTS_OK) return rc;
     c->tblock = 2;
     c->tile2 = TileShape{ty, tz};
     return MTS_OK;
@@ -888,6 +916,7 @@ int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, do
     c->p.diag_every = 0;
     c->timing = false;
     c->tblock = 1;               // single-step shapes first; the choice is set at the end
+    c->mpp = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = MTS_OK;
     auto hip = [&](hipError_t e, const char *what) {
@@ -924,6 +953,30 @@ int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, do
             }
         }
     }
+    // the best single-step configuration again with the momenta written to the other copy
+    bool pick_mpp = false;
+    if (rc == MTS_OK) {
+        c->nt = pick_nt;
+        c->pf = pick_pf;
+        rc = mts_set_tile(c, pick.ty, pick.tz);
+        const int r2 = rc == MTS_OK ? mts_set_momentum_pingpong(c, 1) : rc;
+        if (r2 == MTS_OK) {
+            float ms = 0;
+            if ((rc = mts_step(c, 1, 1.0, 0.5, 1.0)) == MTS_OK && hip(hipEventRecord(e0, c->stream), "hipEventRecord") &&
+                (rc = mts_step(c, steps, 1.1, 0.5, 1.0)) == MTS_OK &&
+                hip(hipEventRecord(e1, c->stream), "hipEventRecord") &&
+                hip(hipEventSynchronize(e1), "hipEventSynchronize") &&
+                hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime") && ms < best) {
+                best = ms;
+                pick_mpp = true;
+            }
+        } else if (r2 != MTS_ENOMEM) {
+            rc = r2;
+        }
+        c->mpp = false;
+        if (rc == MTS_OK) c->err.clear();
+    }
+
     // two steps per sweep (FP32), timed over an even number of steps, per step
     double best_ps = best / steps;
     int pick_tb = 1;
@@ -964,6 +1017,7 @@ int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, do
     }
     c->nt = pick_tb == 2 ? pick2_nt : pick_nt;
     c->pf = pick_pf;
+    c->mpp = pick_mpp;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     c->p.diag_every = d;
@@ -972,7 +1026,7 @@ int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, do
     if ((rc = mts_set_tile(c, pick.ty, pick.tz)) != MTS_OK) return rc;
     if ((rc = mts_set_time_blocking(c, pick_tb, pick2.ty, pick2.tz)) != MTS_OK) return rc;
     if ((rc = mts_init_fields(c, 0)) != MTS_OK) return rc;   // momenta back in the state buffer
-    if (pick_tb == 1 && c->mom2) {                           // the second momentum copy is not needed
+    if (pick_tb == 1 && !pick_mpp && c->mom2) {              // the second momentum copy is not needed
         HIPCHK(c, hipStreamSynchronize(c->stream));
         (void)hipFree(c->mom2);
         c->mom2 = nullptr;

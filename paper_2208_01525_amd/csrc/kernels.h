@@ -105,10 +105,12 @@ hipError_t launch_cool_tile(const Geom &g, Fields<T> in, Fields<T> out, const St
 
 // nt selects streaming (non-temporal) stores for the outputs; pf loads the
 // fields of plain steps one plane further ahead (FP32 diagnostic steps always do).
+// Momenta are read from `mom` and written to `mom_out` (the same copy: in
+// place).
 template <typename T>
-hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, const StepCoef<T> &c,
-                            bool diag, Partials part, TileShape ts, T *alpha, uint32_t plane, bool nt, bool pf,
-                            hipStream_t st);
+hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, Moms<T> mom_out,
+                            const StepCoef<T> &c, bool diag, Partials part, TileShape ts, T *alpha, uint32_t plane,
+                            bool nt, bool pf, hipStream_t st);
 
 // Two steps in one sweep (temporal blocking, FP32): reads fields n from
 // `in` and momenta n - 1/2 from `min_`, writes fields n + 2 to `out` and

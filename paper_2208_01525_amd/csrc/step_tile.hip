@@ -55,7 +55,8 @@ __device__ __forceinline__ cx<T> ldc(const Lds<T, TY> &L, int sec, int q, int i)
 // written.
 template <typename T, bool DIAG, int TY, bool NT, bool COOL = false, int PF = 0>
 __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, const Fields<T> &out,
-                                          const Moms<T> &mom, const StepCoef<T> &c, int X0, int Y0, int Z0, int TZ,
+                                          const Moms<T> &mom, const Moms<T> &mom_out,
+                                          const StepCoef<T> &c, int X0, int Y0, int Z0, int TZ,
                                           Lds<T, TY> &L, double (&acc)[6], T *alpha, uint32_t plane) {
     constexpr int R = TY + 2;
 
@@ -239,9 +240,9 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                 for (int i = 0; i < 3; i++) q.a[i] = cA[sec][i];
                 const SiteOut<T> r = site_update<T, COOL>(c, sec, q);
                 if constexpr (!COOL) {
-                    st_stream<NT>(&mom.pi[sec][s], r.p1);
+                    st_stream<NT>(&mom_out.pi[sec][s], r.p1);
 #pragma unroll
-                    for (int i = 0; i < 3; i++) st_stream<NT>(&mom.E[sec][i][s], r.e1[i]);
+                    for (int i = 0; i < 3; i++) st_stream<NT>(&mom_out.E[sec][i][s], r.e1[i]);
                 }
                 st_stream<NT>(&out.phi[sec][s], r.fn);
 #pragma unroll
@@ -308,13 +309,15 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
 
 template <typename T, bool DIAG, int TY, bool NT, int PF>
 __global__ __launch_bounds__(64 * (TY + 3)) void step_tile_kernel(Geom g, Fields<T> in, Fields<T> out, Moms<T> mom,
+                                                                  Moms<T> mom_out,
                                                                   StepCoef<T> c, Partials part, int TZ, int ntx,
                                                                   int nty, int ntz, T *alpha, uint32_t plane) {
     __shared__ Lds<T, TY> L;
     const uint32_t t = xcd_order(blockIdx.x, (uint32_t)(ntx * nty * ntz));
     const int tx = t % ntx, ty_ = (t / ntx) % nty, tz = t / (ntx * nty);
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    tile_step<T, DIAG, TY, NT, false, PF>(g, in, out, mom, c, tx * 64, ty_ * TY, tz * TZ, TZ, L, acc, alpha, plane);
+    tile_step<T, DIAG, TY, NT, false, PF>(g, in, out, mom, mom_out, c, tx * 64, ty_ * TY, tz * TZ, TZ, L, acc, alpha,
+                                          plane);
     if constexpr (DIAG) block_sum_store<6, TY + 3>(acc, part, SL_EPS, t);
 }
 
@@ -352,7 +355,7 @@ __global__ __launch_bounds__(64 * (TY + 3)) void step_tile_batch_kernel(const Ba
         }
     }
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    tile_step<T, DIAG, TY, NT>(bx.g, fin, fout, mom, coef[lo], tx * 64, ty_ * TY, tz * bx.tz, bx.tz, L, acc,
+    tile_step<T, DIAG, TY, NT>(bx.g, fin, fout, mom, mom, coef[lo], tx * 64, ty_ * TY, tz * bx.tz, bx.tz, L, acc,
                                as_global(bx.alpha), bx.plane);
     if constexpr (DIAG) {
         Partials part = bx.part;
@@ -370,7 +373,7 @@ __global__ __launch_bounds__(64 * (TY + 3)) void cool_tile_kernel(Geom g, Fields
     const int tx = t % ntx, ty_ = (t / ntx) % nty, tz = t / (ntx * nty);
     double acc[6] = {0, 0, 0, 0, 0, 0};
     const Moms<T> none{};
-    tile_step<T, false, TY, true, true>(g, in, out, none, c, tx * 64, ty_ * TY, tz * TZ, TZ, L, acc, nullptr, 0);
+    tile_step<T, false, TY, true, true>(g, in, out, none, none, c, tx * 64, ty_ * TY, tz * TZ, TZ, L, acc, nullptr, 0);
 }
 
 template <typename T>
@@ -400,13 +403,15 @@ uint32_t tile_blocks(const Geom &g, TileShape ts) {
 }
 
 template <typename T, int TY>
-static hipError_t launch_ty(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, const StepCoef<T> &c, bool diag,
+static hipError_t launch_ty(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, Moms<T> mom_out,
+                            const StepCoef<T> &c, bool diag,
                             Partials part, int tz, T *alpha, uint32_t plane, bool nt, bool pf, hipStream_t st) {
     const int ntx = (g.nx + 63) / 64, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + tz - 1) / tz;
     dim3 block(64, TY + 3, 1);
     dim3 grid((unsigned)(ntx * nty * ntz), 1, 1);
 #define MTS_TILE_LAUNCH(D, N, F) \
-    step_tile_kernel<T, D, TY, N, F><<<grid, block, 0, st>>>(g, in, out, mom, c, part, tz, ntx, nty, ntz, alpha, plane)
+    step_tile_kernel<T, D, TY, N, F><<<grid, block, 0, st>>>(g, in, out, mom, mom_out, c, part, tz, ntx, nty, ntz, \
+                                                             alpha, plane)
     if (diag) {
         // FP32 diagnostic steps always load the fields one plane further
         // ahead: at the row counts they run with it costs no occupancy and
@@ -427,12 +432,13 @@ static hipError_t launch_ty(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> 
 }
 
 template <typename T>
-hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, const StepCoef<T> &c, bool diag,
+hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, Moms<T> mom_out,
+                            const StepCoef<T> &c, bool diag,
                             Partials part, TileShape ts, T *alpha, uint32_t plane, bool nt, bool pf, hipStream_t st) {
     switch (ts.ty) {
-        case 4: return launch_ty<T, 4>(g, in, out, mom, c, diag, part, ts.tz, alpha, plane, nt, pf, st);
-        case 8: return launch_ty<T, 8>(g, in, out, mom, c, diag, part, ts.tz, alpha, plane, nt, pf, st);
-        case 12: return launch_ty<T, 12>(g, in, out, mom, c, diag, part, ts.tz, alpha, plane, nt, pf, st);
+        case 4: return launch_ty<T, 4>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, st);
+        case 8: return launch_ty<T, 8>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, st);
+        case 12: return launch_ty<T, 12>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -469,10 +475,10 @@ template hipError_t launch_step_tile_batch<float>(const BatchBox<float> *, int, 
 template hipError_t launch_step_tile_batch<double>(const BatchBox<double> *, int, uint32_t, int,
                                                    const StepCoef<double> *, bool, int, bool, hipStream_t);
 
-template hipError_t launch_step_tile<float>(const Geom &, Fields<float>, Fields<float>, Moms<float>,
+template hipError_t launch_step_tile<float>(const Geom &, Fields<float>, Fields<float>, Moms<float>, Moms<float>,
                                             const StepCoef<float> &, bool, Partials, TileShape, float *, uint32_t,
                                             bool, bool, hipStream_t);
-template hipError_t launch_step_tile<double>(const Geom &, Fields<double>, Fields<double>, Moms<double>,
+template hipError_t launch_step_tile<double>(const Geom &, Fields<double>, Fields<double>, Moms<double>, Moms<double>,
                                              const StepCoef<double> &, bool, Partials, TileShape, double *, uint32_t,
                                              bool, bool, hipStream_t);
 

@@ -259,28 +259,59 @@ def test_small_workload_full_run(precision):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_tile_shapes_bitwise_identical(precision):
-    """Every tile shape of the z-marching kernel, with streaming or plain stores and
-    with or without the deeper load pipeline, gives the same fields bit for bit (on
-    a box with ragged tiles in every direction)."""
+    """Every tile shape of the z-marching kernel, with streaming or plain stores, with or
+    without the deeper load pipeline and with the momenta rewritten in place or written to
+    the second copy, gives the same fields bit for bit (on a box with ragged tiles in every
+    direction; 12 steps with diagnostics every 4, so the momenta end in either copy)."""
     nx, ny, nz = 70, 21, 13
     st = rounded(I.random_full(nx, ny, nz, 11, link=0.5, mom=0.5), precision)
     ref = None
-    for ty, tz, nt, pf in ((8, 32, True, False), (4, 1, False, False), (12, 5, True, True), (4, 7, True, True),
-                           (8, 13, False, True), (8, 32, False, False), (12, 64, True, True), (8, 2, True, True)):
+    for ty, tz, nt, pf, pp in ((8, 32, True, False, False), (4, 1, False, False, True), (12, 5, True, True, False),
+                               (4, 7, True, True, True), (8, 13, False, True, False), (8, 32, False, False, True),
+                               (12, 64, True, True, True), (8, 2, True, True, False)):
         lat = lattice(nx, ny, nz, precision, eta_ref=9.0, diag_every=4)
         lat.set_tile(ty, tz)
         lat.set_streaming_stores(nt)
         lat.set_prefetch(pf)
+        lat.set_momentum_pingpong(pp)
         lat.set_fields(st)
         lat.step(12, 1.0, 0.5, 1.0)
         got = lat.get_fields()
         recs = lat.diagnostics()
         if ref is None:
             ref, rrec = got, recs
-        assert np.array_equal(got, ref), (ty, tz, nt, pf)
+        assert np.array_equal(got, ref), (ty, tz, nt, pf, pp)
         for a, b in zip(recs, rrec):
             assert a["sum_energy"] == pytest.approx(b["sum_energy"], rel=1e-13)
             assert a["wind_abs"] == b["wind_abs"] and a["pq_count2"] == b["pq_count2"]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_momentum_pingpong_checkpoint(precision):
+    """With momentum ping-pong an odd number of steps leaves the momenta in the second copy:
+    the host copy taken there and restored into a context without it continues bit for bit,
+    and so does switching it off mid-run.  (Diagnostic steps with ping-pong are covered by
+    the tile-shape test; here none are due, so that a restarted step count does not move them.)"""
+    nx, ny, nz = 40, 18, 12
+    st = rounded(I.random_full(nx, ny, nz, 23, link=0.5, mom=0.5), precision)
+    whole = lattice(nx, ny, nz, precision, eta_ref=5.0)
+    whole.set_fields(st)
+    whole.step(5, 1.0, 0.5, 1.0)            # two calls, as below: eta_j = eta0 + j k of each call
+    whole.step(5, 1.5, 0.5, 1.0)
+    a = lattice(nx, ny, nz, precision, eta_ref=5.0)
+    a.set_momentum_pingpong(True)
+    assert a.get_momentum_pingpong()
+    a.set_fields(st)
+    a.step(5, 1.0, 0.5, 1.0)
+    mid = a.get_fields()
+    b = lattice(nx, ny, nz, precision, eta_ref=5.0)
+    b.set_fields(mid)
+    b.step(5, 1.5, 0.5, 1.0)
+    a.set_momentum_pingpong(False)
+    a.step(5, 1.5, 0.5, 1.0)
+    ref = whole.get_fields()
+    assert np.array_equal(a.get_fields(), ref)
+    assert np.array_equal(b.get_fields(), ref)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])

@@ -233,8 +233,8 @@ int mts_get_streaming_stores(const mts_ctx *ctx, int32_t *on);
  * copy the library allocates on first use, 40 bytes per site in FP32, 80 in
  * FP64, freed by mts_destroy) instead of rewriting them in place, which HBM
  * serves a few per cent faster; MTS_ENOMEM if the copy does not fit.
- * Results are bitwise identical; steps on the per-site kernel stay in
- * place.  on = 0 (the default) rewrites in place.  The autotuner tries it.
+ * Results are bitwise identical; diagnostic steps and steps on the
+ * per-site kernel stay in place.  on = 0 (the default) rewrites in place.  The autotuner tries it.
  * Synchronises the stream.  Update of Sec. III. */
 int mts_set_momentum_pingpong(mts_ctx *ctx, int32_t on);
 int mts_get_momentum_pingpong(const mts_ctx *ctx, int32_t *on);

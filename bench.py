@@ -139,7 +139,8 @@ def run_batch(P, torch, steps, small=48, big=16, tune_steps=3):
     """Ensemble of uneven boxes: `small` boxes of 128^3 and `big` of 256^3; box b has seed
     1000 + b, m = 1/2 (b even) or 2/3 (b odd), s = 0 if b//2 is even else 1; all FP32, dx = 0.5,
     dt = 0.1, kappa = 0.9, diagnostics every 10 steps, `steps` steps from eta = 1 with a = 1 at
-    the end, all advanced by one graph launch; tile shape from the autotuner."""
+    the end, all advanced by one graph launch; tile shape, streaming stores and momentum ping-pong from
+    the autotuner."""
     nb = small + big
     eta_end = 1.0 + steps * 0.1
     params = [P.make_params(128 if b < small else 256, precision="fp32", eta_ref=eta_end, diag_every=10)
@@ -161,7 +162,8 @@ def run_batch(P, torch, steps, small=48, big=16, tune_steps=3):
     achieved = BYTES_PER_SITE["fp32"] * sites * steps / (tm["ms"] * 1e-3) / 1e9
     out = {"value": sites * steps / wall, "unit": "site-updates/s", "boxes": f"{small}x128^3 + {big}x256^3",
            "sites": sites, "steps": steps, "ms_per_step": 1e3 * wall / steps, "graph_ms": tm["ms"],
-           "tile": [ty, tz], "streaming_stores": bt.get_streaming_stores(), "autotune_ms_per_step": tune_ms,
+           "tile": [ty, tz], "streaming_stores": bt.get_streaming_stores(),
+           "momentum_pingpong": bt.get_momentum_pingpong(), "autotune_ms_per_step": tune_ms,
            "records_per_box": min(nrec),
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,

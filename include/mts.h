@@ -346,12 +346,22 @@ int mts_batch_set_tile(mts_batch *b, int32_t ty, const int32_t *tz);
 int mts_batch_set_streaming_stores(mts_batch *b, int32_t on);
 int mts_batch_get_streaming_stores(const mts_batch *b, int32_t *on);
 
+/* Momentum ping-pong for the batched launch, as mts_set_momentum_pingpong:
+ * plain steps of every box read the momenta from one copy and write them to
+ * the other (each box's second copy is allocated by the library on first
+ * use, freed by mts_batch_destroy); diagnostic steps stay in place.  Results
+ * are bitwise identical; off (0) by default; the batch autotuner tries it.
+ * Synchronises the batch's and the caller's streams.  Update of Sec. III. */
+int mts_batch_set_momentum_pingpong(mts_batch *b, int32_t on);
+int mts_batch_get_momentum_pingpong(const mts_batch *b, int32_t *on);
+
 /* Summed HIP-event time (ms) of the graph launches and the steps they ran
  * since the last read; synchronises. */
 int mts_batch_timing_read(mts_batch *b, int64_t *steps, double *ms);
 
-/* Autotuner of the batched launch (one ty and one tz for all boxes), as
- * mts_autotune; overwrites every box. */
+/* Autotuner of the batched launch (one ty and one tz for all boxes, streaming
+ * stores, then momentum ping-pong on the best of those), as mts_autotune;
+ * overwrites every box. */
 int mts_batch_autotune(mts_batch *b, int32_t steps, int32_t *ty, int32_t *tz, double *ms_per_step);
 
 const char *mts_batch_last_error(const mts_batch *b);

@@ -787,7 +787,7 @@ int mts_set_streaming_stores(mts_ctx *c, int32_t on) {
 }
 
 // The second momentum copy (10 planes), allocated on first use.
-int ensure_mom2(mts_ctx *c, const char *what) {
+static int ensure_mom2(mts_ctx *c, const char *what) {
     if (c->mom2) return MTS_OK;
     hipError_t e = hipMalloc(&c->mom2, (size_t)10 * c->plane * c->esz);
     if (e != hipSuccess) {
@@ -1103,6 +1103,7 @@ struct mts_batch {
     int32_t ty_diag = 8;
     uint32_t nblk_diag = 0;
     bool nt = true;                  // streaming stores in the tiled update
+    bool mpp = false;                // plain tiled steps write the momenta to the other copy
     void *coef_dev = nullptr;        // StepCoef<T>[n][nbox]
     size_t coef_cap = 0;             // bytes
     int32_t ty = 8;
@@ -1148,7 +1149,8 @@ int batch_upload_boxes(mts_batch *b) {
             x.g = c->g;
             x.f[0] = fields_of<T>(c, 0);
             x.f[1] = fields_of<T>(c, 1);
-            x.mom = moms_of<T>(c);
+            x.mom[0] = moms_at<T>(c, 0);
+            x.mom[1] = moms_at<T>(c, c->mom2 ? 1 : 0);
             x.part = Partials{c->partials, c->maxblk};
             x.alpha = static_cast<T *>(c->alpha);
             x.plane = (uint32_t)c->plane;
@@ -1228,18 +1230,19 @@ int batch_step_t(mts_batch *b, int32_t n, const double *eta0, const double *era_
     // Host bookkeeping advances while the steps are captured; nothing runs
     // until the graph is launched, so a failure before that restores it.
     struct Saved {
-        int cur;
+        int cur, mcur;
         int64_t step_count, produced, cells_step;
         size_t nmeta;
         bool have_cells;
     };
     std::vector<Saved> saved;
     for (mts_ctx *c : b->box)
-        saved.push_back({c->cur, c->step_count, c->produced, c->cells_step, c->meta.size(), c->have_cells});
+        saved.push_back({c->cur, c->mcur, c->step_count, c->produced, c->cells_step, c->meta.size(), c->have_cells});
     auto rollback = [&](int code, const std::string &why) {
         for (size_t k = 0; k < nbox; k++) {
             mts_ctx *c = b->box[k];
             c->cur = saved[k].cur;
+            c->mcur = saved[k].mcur;
             c->step_count = saved[k].step_count;
             c->produced = saved[k].produced;
             c->cells_step = saved[k].cells_step;
@@ -1267,10 +1270,14 @@ int batch_step_t(mts_batch *b, int32_t n, const double *eta0, const double *era_
                                      tab[(size_t)j * nbox + k], true, Partials{c->partials, c->maxblk}, b->stream);
             }
         } else {
+            // momenta to the other copy on plain steps under ping-pong, in place otherwise
+            const int mpin = c0->mcur, mpout = b->mpp && !diag ? 1 - mpin : mpin;
             err = launch_step_tile_batch<T>(static_cast<const BatchBox<T> *>(diag ? b->boxes_diag_dev : b->boxes_dev),
-                                            (int)nbox, diag ? b->nblk_diag : b->nblk, c0->cur,
+                                            (int)nbox, diag ? b->nblk_diag : b->nblk, c0->cur, mpin, mpout,
                                             static_cast<const StepCoef<T> *>(b->coef_dev) + (size_t)j * nbox, diag,
                                             diag ? b->ty_diag : b->ty, b->nt, b->stream);
+            if (mpout != mpin)
+                for (mts_ctx *c : b->box) c->mcur = mpout;
         }
         if (diag)
             for (size_t k = 0; k < nbox && err == hipSuccess; k++)
@@ -1403,7 +1410,7 @@ int mts_batch_step(mts_batch *b, int32_t n, const double *eta0, const double *er
         const double sw = eta_switch ? eta_switch[k] : INFINITY;
         const int rc = check_step(c, n, eta0[k], era_m[k], s_before[k], sa, sw);
         if (rc != MTS_OK) return bfail(b, rc, "box " + std::to_string(k) + ": " + c->err);
-        if (c->cur != b->box[0]->cur || c->step_count != b->box[0]->step_count)
+        if (c->cur != b->box[0]->cur || c->mcur != b->box[0]->mcur || c->step_count != b->box[0]->step_count)
             return bfail(b, MTS_EINVAL, "boxes must be initialised and stepped together");
     }
     if (n == 0) return MTS_OK;
@@ -1451,6 +1458,28 @@ int mts_batch_get_streaming_stores(const mts_batch *b, int32_t *on) {
     return MTS_OK;
 }
 
+int mts_batch_set_momentum_pingpong(mts_batch *b, int32_t on) {
+    if (!b) return MTS_EINVAL;
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->user));
+    if (on) {
+        for (size_t k = 0; k < b->box.size(); k++) {
+            const int rc = ensure_mom2(b->box[k], "momentum ping-pong");
+            if (rc != MTS_OK) return bfail(b, rc, "box " + std::to_string(k) + ": " + b->box[k]->err);
+        }
+        const int rc = batch_upload(b);
+        if (rc != MTS_OK) return rc;
+    }
+    b->mpp = on != 0;
+    return MTS_OK;
+}
+
+int mts_batch_get_momentum_pingpong(const mts_batch *b, int32_t *on) {
+    if (!b || !on) return MTS_EINVAL;
+    *on = b->mpp ? 1 : 0;
+    return MTS_OK;
+}
+
 int mts_batch_timing_read(mts_batch *b, int64_t *steps, double *ms) {
     if (!b) return MTS_EINVAL;
     BHIPCHK(b, hipStreamSynchronize(b->stream));
@@ -1474,6 +1503,7 @@ int mts_batch_autotune(mts_batch *b, int32_t steps, int32_t *ty_out, int32_t *tz
     }
     std::vector<uint64_t> seeds(nbox, 0);
     std::vector<double> eta(nbox, 1.0), era(nbox, 0.5), sv(nbox, 1.0);
+    b->mpp = false;
     int rc = mts_batch_init_fields(b, seeds.data());
     double best = INFINITY;
     int pick_ty = b->ty, pick_tz = b->tz.empty() ? 32 : b->tz[0];
@@ -1502,11 +1532,42 @@ int mts_batch_autotune(mts_batch *b, int32_t steps, int32_t *ty_out, int32_t *tz
             }
         }
     b->nt = pick_nt;
+    // the best configuration again with the momenta written to the other copy
+    bool pick_mpp = false;
+    if (rc == MTS_OK) {
+        std::vector<int32_t> tzv(nbox, pick_tz);
+        rc = mts_batch_set_tile(b, pick_ty, tzv.data());
+        const int r2 = rc == MTS_OK ? mts_batch_set_momentum_pingpong(b, 1) : rc;
+        if (r2 == MTS_OK) {
+            int64_t ns = 0;
+            double ms = 0;
+            if ((rc = mts_batch_step(b, 1, eta.data(), era.data(), sv.data(), nullptr, nullptr)) == MTS_OK &&
+                (rc = mts_batch_timing_read(b, &ns, &ms)) == MTS_OK &&
+                (rc = mts_batch_step(b, steps, eta.data(), era.data(), sv.data(), nullptr, nullptr)) == MTS_OK &&
+                (rc = mts_batch_timing_read(b, &ns, &ms)) == MTS_OK && ms < best) {
+                best = ms;
+                pick_mpp = true;
+            }
+        } else if (r2 != MTS_ENOMEM) {
+            rc = r2;
+        }
+        b->mpp = false;
+        if (rc == MTS_OK) b->err.clear();
+    }
     for (size_t k = 0; k < nbox; k++) b->box[k]->p.diag_every = d[k];
     if (rc != MTS_OK) return rc;
     std::vector<int32_t> tzv(nbox, pick_tz);
     if ((rc = mts_batch_set_tile(b, pick_ty, tzv.data())) != MTS_OK) return rc;
-    if ((rc = mts_batch_init_fields(b, seeds.data())) != MTS_OK) return rc;
+    if ((rc = mts_batch_init_fields(b, seeds.data())) != MTS_OK) return rc;   // momenta back in copy 0
+    if ((rc = mts_batch_set_momentum_pingpong(b, pick_mpp ? 1 : 0)) != MTS_OK) return rc;
+    if (!pick_mpp) {                                  // the second momentum copies are not needed
+        BHIPCHK(b, hipStreamSynchronize(b->stream));
+        for (mts_ctx *c : b->box) {
+            (void)hipFree(c->mom2);
+            c->mom2 = nullptr;
+        }
+        if ((rc = batch_upload(b)) != MTS_OK) return rc;
+    }
     if (ty_out) *ty_out = pick_ty;
     if (tz_out) *tz_out = pick_tz;
     if (ms_out) *ms_out = best / steps;

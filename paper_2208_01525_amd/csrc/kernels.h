@@ -127,16 +127,18 @@ template <typename T>
 struct BatchBox {
     Geom g;
     Fields<T> f[2];       // field copies 0 and 1
-    Moms<T> mom;
+    Moms<T> mom[2];       // momentum copies 0 and 1 (both the state buffer's without a second copy)
     Partials part;        // this box's partials (box-local block index)
     T *alpha;             // this box's phase scratch [2][plane]
     uint32_t plane;
     int32_t ntx, nty, ntz, tz;
     uint32_t blk0;        // first block of this box in the launch
 };
+// Fields from copy `parity` to the other; momenta from copy `mpin` to copy
+// `mpout` (equal: in place).
 template <typename T>
-hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32_t nblk, int parity,
-                                  const StepCoef<T> *coef_dev, bool diag, int ty, bool nt, hipStream_t st);
+hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32_t nblk, int parity, int mpin,
+                                  int mpout, const StepCoef<T> *coef_dev, bool diag, int ty, bool nt, hipStream_t st);
 
 // Phase alpha = arg(phi) of every site and sector into alpha[2][plane]
 // (NaN where phi = 0), input of the winding kernel.

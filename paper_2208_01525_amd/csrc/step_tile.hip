@@ -326,8 +326,8 @@ __global__ __launch_bounds__(64 * (TY + 3)) void step_tile_kernel(Geom g, Fields
 // partials (indexed by the box-local block).
 template <typename T, bool DIAG, int TY, bool NT>
 __global__ __launch_bounds__(64 * (TY + 3)) void step_tile_batch_kernel(const BatchBox<T> *boxes, int nbox,
-                                                                        int parity, const StepCoef<T> *coef,
-                                                                        uint32_t nblk) {
+                                                                        int parity, int mpin, int mpout,
+                                                                        const StepCoef<T> *coef, uint32_t nblk) {
     __shared__ Lds<T, TY> L;
     const uint32_t t = xcd_order(blockIdx.x, nblk);
     int lo = 0, hi = nbox - 1;             // last box with blk0 <= t
@@ -341,21 +341,23 @@ __global__ __launch_bounds__(64 * (TY + 3)) void step_tile_batch_kernel(const Ba
     const int tx = lt % bx.ntx, ty_ = (lt / bx.ntx) % bx.nty, tz = lt / (bx.ntx * bx.nty);
     // the box table's pointers all address global memory
     Fields<T> fin, fout;
-    Moms<T> mom;
+    Moms<T> mom, mom_out;
 #pragma unroll
     for (int sec = 0; sec < 2; sec++) {
         fin.phi[sec] = as_global(bx.f[parity].phi[sec]);
         fout.phi[sec] = as_global(bx.f[1 - parity].phi[sec]);
-        mom.pi[sec] = as_global(bx.mom.pi[sec]);
+        mom.pi[sec] = as_global(bx.mom[mpin].pi[sec]);
+        mom_out.pi[sec] = as_global(bx.mom[mpout].pi[sec]);
 #pragma unroll
         for (int i = 0; i < 3; i++) {
             fin.A[sec][i] = as_global(bx.f[parity].A[sec][i]);
             fout.A[sec][i] = as_global(bx.f[1 - parity].A[sec][i]);
-            mom.E[sec][i] = as_global(bx.mom.E[sec][i]);
+            mom.E[sec][i] = as_global(bx.mom[mpin].E[sec][i]);
+            mom_out.E[sec][i] = as_global(bx.mom[mpout].E[sec][i]);
         }
     }
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    tile_step<T, DIAG, TY, NT>(bx.g, fin, fout, mom, mom, coef[lo], tx * 64, ty_ * TY, tz * bx.tz, bx.tz, L, acc,
+    tile_step<T, DIAG, TY, NT>(bx.g, fin, fout, mom, mom_out, coef[lo], tx * 64, ty_ * TY, tz * bx.tz, bx.tz, L, acc,
                                as_global(bx.alpha), bx.plane);
     if constexpr (DIAG) {
         Partials part = bx.part;
@@ -444,12 +446,12 @@ hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> 
 }
 
 template <typename T>
-hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32_t nblk, int parity,
-                                  const StepCoef<T> *coef_dev, bool diag, int ty, bool nt, hipStream_t st) {
+hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32_t nblk, int parity, int mpin,
+                                  int mpout, const StepCoef<T> *coef_dev, bool diag, int ty, bool nt, hipStream_t st) {
     dim3 grid(nblk, 1, 1);
 #define MTS_BATCH_LAUNCH(TYV, D, N)                                                                                 \
-    step_tile_batch_kernel<T, D, TYV, N><<<grid, dim3(64, TYV + 3, 1), 0, st>>>(boxes_dev, nbox, parity, coef_dev, \
-                                                                                 nblk)
+    step_tile_batch_kernel<T, D, TYV, N><<<grid, dim3(64, TYV + 3, 1), 0, st>>>(boxes_dev, nbox, parity, mpin,   \
+                                                                                 mpout, coef_dev, nblk)
 #define MTS_BATCH_CASE(TYV)                                           \
     case TYV:                                                         \
         if (diag) {                                                   \
@@ -470,9 +472,9 @@ hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32
 #undef MTS_BATCH_LAUNCH
 }
 
-template hipError_t launch_step_tile_batch<float>(const BatchBox<float> *, int, uint32_t, int, const StepCoef<float> *,
-                                                  bool, int, bool, hipStream_t);
-template hipError_t launch_step_tile_batch<double>(const BatchBox<double> *, int, uint32_t, int,
+template hipError_t launch_step_tile_batch<float>(const BatchBox<float> *, int, uint32_t, int, int, int,
+                                                  const StepCoef<float> *, bool, int, bool, hipStream_t);
+template hipError_t launch_step_tile_batch<double>(const BatchBox<double> *, int, uint32_t, int, int, int,
                                                    const StepCoef<double> *, bool, int, bool, hipStream_t);
 
 template hipError_t launch_step_tile<float>(const Geom &, Fields<float>, Fields<float>, Moms<float>, Moms<float>,

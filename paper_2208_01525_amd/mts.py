@@ -22,7 +22,8 @@ EXPORTS = ("mts_state_bytes", "mts_create", "mts_destroy", "mts_init_fields", "m
            "mts_timing_read", "mts_set_time_blocking", "mts_get_time_blocking", "mts_set_prefetch", "mts_get_prefetch", "mts_set_momentum_pingpong", "mts_get_momentum_pingpong", "mts_last_error", "mts_strerror",
            "mts_batch_state_bytes", "mts_batch_create", "mts_batch_destroy", "mts_batch_size",
            "mts_batch_init_fields", "mts_batch_step", "mts_batch_diagnostics", "mts_batch_get_fields",
-           "mts_batch_set_fields", "mts_batch_set_tile", "mts_batch_set_streaming_stores", "mts_batch_get_streaming_stores", "mts_batch_timing_read", "mts_batch_autotune",
+           "mts_batch_set_fields", "mts_batch_set_tile", "mts_batch_set_streaming_stores", "mts_batch_get_streaming_stores", "mts_batch_set_momentum_pingpong",
+           "mts_batch_get_momentum_pingpong", "mts_batch_timing_read", "mts_batch_autotune",
            "mts_batch_last_error")
 
 
@@ -112,6 +113,8 @@ def load():
     L.mts_batch_set_streaming_stores.argtypes = [vp, ctypes.c_int32]
     L.mts_get_streaming_stores.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.mts_batch_get_streaming_stores.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.mts_batch_set_momentum_pingpong.argtypes = [vp, ctypes.c_int32]
+    L.mts_batch_get_momentum_pingpong.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.mts_get_tile.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     i32p = ctypes.POINTER(ctypes.c_int32)
     L.mts_autotune.argtypes = [vp, ctypes.c_int32, i32p, i32p, ctypes.POINTER(ctypes.c_double)]
@@ -425,6 +428,14 @@ class Batch:
     def get_streaming_stores(self):
         v = ctypes.c_int32()
         self._check(self.L.mts_batch_get_streaming_stores(self.b, ctypes.byref(v)))
+        return bool(v.value)
+
+    def set_momentum_pingpong(self, on):
+        self._check(self.L.mts_batch_set_momentum_pingpong(self.b, 1 if on else 0))
+
+    def get_momentum_pingpong(self):
+        v = ctypes.c_int32()
+        self._check(self.L.mts_batch_get_momentum_pingpong(self.b, ctypes.byref(v)))
         return bool(v.value)
 
     def timing_read(self):

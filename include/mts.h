@@ -211,12 +211,12 @@ typedef struct mts_segments_t {
 } mts_segments_t;
 int mts_segments(mts_ctx *ctx, double min_length, mts_segments_t *out, int64_t *sizes, int64_t cap, int64_t *n_sizes);
 
-/* Choose the update kernel.  ty in {4, 8, 12} selects the z-marching
- * LDS-tiled kernel with tiles of 64 x ty sites and tz >= 1 planes per
- * workgroup (default 8 x 32 in FP32, 4 x 32 in FP64; diagnostic steps use
- * at most 8 rows in FP32 and 4 in FP64, where their variant does not
- * spill registers); every tile shape gives bitwise identical
- * results.  ty = 0 selects the one-thread-per-site kernel, which computes
+/* Choose the update kernel.  ty in {4, 5, 8, 12} (and 13 in FP32) selects
+ * the z-marching LDS-tiled kernel with tiles of 64 x ty sites and tz >= 1
+ * planes per workgroup (default 8 x 32 in FP32, 4 x 32 in FP64; FP32
+ * diagnostic steps use at most 8 rows, where their variant does not spill
+ * registers, and FP64 diagnostic steps the per-site kernel); every tile
+ * shape gives bitwise identical results.  ty = 0 selects the one-thread-per-site kernel, which computes
  * the plaquette sines directly and agrees with the tiled kernel to
  * rounding.  Synchronises the stream.  EINVAL for other shapes. */
 int mts_set_tile(mts_ctx *ctx, int32_t ty, int32_t tz);
@@ -263,7 +263,7 @@ int mts_set_time_blocking(mts_ctx *ctx, int32_t steps, int32_t ty, int32_t tz);
 int mts_get_time_blocking(const mts_ctx *ctx, int32_t *steps, int32_t *ty, int32_t *tz);
 
 /* Autotuner: time `steps` plain steps of every supported tile shape
- * (ty in {4, 8, 12} -- {4, 8} in FP64 -- by tz in {8, 16, 32, 64}, with and
+ * (ty in {4, 8, 12, 13} -- {4, 5, 8} in FP64 -- by tz in {8, 16, 32, 64}, with and
  * without streaming stores) on this
  * box with HIP events, keep the fastest, and report it (and its ms per
  * step), each with and without the deeper load pipeline

@@ -529,7 +529,7 @@ int mts_create(const mts_params *p, void *dev_state, size_t state_bytes, void *s
     c->stream = static_cast<hipStream_t>(stream);
     c->tile = p->precision == MTS_FP64 ? TileShape{4, 32} : TileShape{8, 32};
     c->maxblk = site_blocks(c->g);
-    for (int ty : {4, 8, 12}) c->maxblk = std::max(c->maxblk, tile_blocks(c->g, TileShape{ty, 1}));
+    for (int ty : {4, 5, 8, 12, 13}) c->maxblk = std::max(c->maxblk, tile_blocks(c->g, TileShape{ty, 1}));
     c->maxblk = std::max(c->maxblk, std::max(wind_blocks(c->g), overlap_blocks(c->g)));
     hipError_t e = hipMalloc(&c->partials, sizeof(double) * NSLOT * (size_t)c->maxblk);
     if (e == hipSuccess) e = hipMalloc(&c->nblk_dev, sizeof(uint32_t) * NSLOT);
@@ -772,7 +772,8 @@ int mts_segments(mts_ctx *c, double min_length, mts_segments_t *out, int64_t *si
 int mts_set_tile(mts_ctx *c, int32_t ty, int32_t tz) {
     if (!c) return MTS_EINVAL;
     const TileShape ts{ty, tz};
-    if (ty != 0 && !tile_supported(ts)) return fail(c, MTS_EINVAL, "tile: ty must be 0, 4, 8 or 12 and tz >= 1");
+    if (ty != 0 && !tile_supported(ts, c->p.precision == MTS_FP64))
+        return fail(c, MTS_EINVAL, "tile: ty must be 0, 4, 5, 8, 12 or (FP32) 13 and tz >= 1");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->tile = ts;
     HIPCHK(c, upload_nblk(c));
@@ -909,7 +910,7 @@ int mts_get_time_blocking(const mts_ctx *c, int32_t *steps, int32_t *ty, int32_t
 
 int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, double *ms_out) {
     if (!c || steps < 1) return MTS_EINVAL;
-    const std::vector<int> tys = c->p.precision == MTS_FP64 ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 12};
+    const std::vector<int> tys = c->p.precision == MTS_FP64 ? std::vector<int>{4, 5, 8} : std::vector<int>{4, 8, 12, 13};
     const int tzs[] = {8, 16, 32, 64};
     // time the plain update, outside the caller's timing; every exit below
     // restores these settings
@@ -1435,7 +1436,7 @@ int mts_batch_set_fields(mts_batch *b, int32_t box, const double *host) {
 
 int mts_batch_set_tile(mts_batch *b, int32_t ty, const int32_t *tz) {
     if (!b || !tz) return MTS_EINVAL;
-    if (!tile_supported(TileShape{ty, 1})) return bfail(b, MTS_EINVAL, "ty must be 4, 8 or 12");
+    if (!batch_tile_supported(TileShape{ty, 1})) return bfail(b, MTS_EINVAL, "ty must be 4, 8 or 12");
     for (size_t k = 0; k < b->box.size(); k++)
         if (tz[k] < 1) return bfail(b, MTS_EINVAL, "tz must be >= 1");
     BHIPCHK(b, hipStreamSynchronize(b->stream));

@@ -381,9 +381,11 @@ __global__ __launch_bounds__(64 * (TY + 3)) void cool_tile_kernel(Geom g, Fields
 template <typename T>
 hipError_t launch_cool_tile(const Geom &g, Fields<T> in, Fields<T> out, const StepCoef<T> &c, TileShape ts,
                             hipStream_t st) {
-    const int ntx = (g.nx + 63) / 64, nty = (g.ny + ts.ty - 1) / ts.ty, ntz = (g.nz + ts.tz - 1) / ts.tz;
+    // the cooling kernel has 4, 8 and 12 rows; tile shapes do not change results
+    const int cty = ts.ty == 5 ? 4 : ts.ty == 13 ? 12 : ts.ty;
+    const int ntx = (g.nx + 63) / 64, nty = (g.ny + cty - 1) / cty, ntz = (g.nz + ts.tz - 1) / ts.tz;
     const dim3 grid((unsigned)(ntx * nty * ntz), 1, 1);
-    switch (ts.ty) {
+    switch (cty) {
         case 4: cool_tile_kernel<T, 4><<<grid, dim3(64, 7, 1), 0, st>>>(g, in, out, c, ts.tz, ntx, nty, ntz); break;
         case 8: cool_tile_kernel<T, 8><<<grid, dim3(64, 11, 1), 0, st>>>(g, in, out, c, ts.tz, ntx, nty, ntz); break;
         case 12: cool_tile_kernel<T, 12><<<grid, dim3(64, 15, 1), 0, st>>>(g, in, out, c, ts.tz, ntx, nty, ntz); break;
@@ -397,7 +399,16 @@ template hipError_t launch_cool_tile<float>(const Geom &, Fields<float>, Fields<
 template hipError_t launch_cool_tile<double>(const Geom &, Fields<double>, Fields<double>, const StepCoef<double> &,
                                              TileShape, hipStream_t);
 
-bool tile_supported(TileShape ts) { return (ts.ty == 4 || ts.ty == 8 || ts.ty == 12) && ts.tz >= 1; }
+// Rows per tile: 4, 5, 8 and 12 in both precisions, 13 in FP32 (whose
+// workgroup of 16 waves fills a CU's wave slots at 128 registers; in FP64 its
+// LDS does not fit).  5 rows make 8 waves, the two-per-SIMD that FP64's
+// 240-256 registers allow.
+bool tile_supported(TileShape ts, bool fp64) {
+    const bool ok = ts.ty == 4 || ts.ty == 5 || ts.ty == 8 || ts.ty == 12 || (ts.ty == 13 && !fp64);
+    return ok && ts.tz >= 1;
+}
+
+bool batch_tile_supported(TileShape ts) { return (ts.ty == 4 || ts.ty == 8 || ts.ty == 12) && ts.tz >= 1; }
 
 uint32_t tile_blocks(const Geom &g, TileShape ts) {
     const uint32_t ntx = (g.nx + 63) / 64, nty = (g.ny + ts.ty - 1) / ts.ty, ntz = (g.nz + ts.tz - 1) / ts.tz;
@@ -418,10 +429,16 @@ static hipError_t launch_ty(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> 
         // FP32 diagnostic steps always load the fields one plane further
         // ahead: at the row counts they run with it costs no occupancy and
         // saves about 5 % (512^3: 4.82 against 5.08 ms).  The FP64 variant
-        // is at its register limit already.
+        // is at its register limit already.  Diagnostic steps run at most 8
+        // rows in FP32 and on the per-site kernel in FP64, so the shapes
+        // only plain steps use have no diagnostic variant.
         constexpr int DPF = sizeof(T) == 4 ? 1 : 0;
-        if (nt) MTS_TILE_LAUNCH(true, true, DPF);
-        else MTS_TILE_LAUNCH(true, false, DPF);
+        if constexpr (TY == 13 || (TY == 5 && sizeof(T) == 8)) {
+            return hipErrorNotSupported;
+        } else {
+            if (nt) MTS_TILE_LAUNCH(true, true, DPF);
+            else MTS_TILE_LAUNCH(true, false, DPF);
+        }
     } else if (pf) {
         if (nt) MTS_TILE_LAUNCH(false, true, 1);
         else MTS_TILE_LAUNCH(false, false, 1);
@@ -440,7 +457,13 @@ hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> 
     switch (ts.ty) {
         case 4: return launch_ty<T, 4>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, st);
         case 8: return launch_ty<T, 8>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, st);
+        case 5: return launch_ty<T, 5>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, st);
         case 12: return launch_ty<T, 12>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, st);
+        case 13:
+            if constexpr (sizeof(T) == 4)
+                return launch_ty<T, 13>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, st);
+            else
+                return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }

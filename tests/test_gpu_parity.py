@@ -266,9 +266,13 @@ def test_tile_shapes_bitwise_identical(precision):
     nx, ny, nz = 70, 21, 13
     st = rounded(I.random_full(nx, ny, nz, 11, link=0.5, mom=0.5), precision)
     ref = None
-    for ty, tz, nt, pf, pp in ((8, 32, True, False, False), (4, 1, False, False, True), (12, 5, True, True, False),
-                               (4, 7, True, True, True), (8, 13, False, True, False), (8, 32, False, False, True),
-                               (12, 64, True, True, True), (8, 2, True, True, False)):
+    shapes = [(8, 32, True, False, False), (4, 1, False, False, True), (12, 5, True, True, False),
+              (4, 7, True, True, True), (8, 13, False, True, False), (8, 32, False, False, True),
+              (12, 64, True, True, True), (8, 2, True, True, False), (5, 3, True, False, True),
+              (5, 32, False, True, False)]
+    if precision == "fp32":
+        shapes += [(13, 6, True, False, True), (13, 64, False, True, False)]
+    for ty, tz, nt, pf, pp in shapes:
         lat = lattice(nx, ny, nz, precision, eta_ref=9.0, diag_every=4)
         lat.set_tile(ty, tz)
         lat.set_streaming_stores(nt)
@@ -328,6 +332,9 @@ def test_site_kernel_agrees_with_tiled_kernel(precision):
     assert np.abs(out[0] - out[1]).max() <= 1e3 * U[precision] * np.abs(out[0]).max()
     with pytest.raises(P.MtsError):
         lat.set_tile(6, 8)
+    if precision == "fp64":
+        with pytest.raises(P.MtsError):
+            lat.set_tile(13, 8)                 # its LDS does not fit in FP64
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
@@ -466,7 +473,7 @@ def test_full_size_workload_sampled():
     assert r["wind_abs"][0] == np.abs(W_all[:3]).sum() and r["wind_abs"][1] == np.abs(W_all[3:]).sum()
 
 
-@pytest.mark.parametrize("tile", [(8, 32), (12, 5), (0, 8)])
+@pytest.mark.parametrize("tile", [(8, 32), (12, 5), (0, 8), (5, 4)])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_cooling_parity(precision, tile):
     """Diffusive cooling (Sec. III) on the GPU against the oracle: 30 steps of 1/30 from

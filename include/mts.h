@@ -340,8 +340,8 @@ int mts_batch_diagnostics(mts_batch *b, int32_t box, mts_diag *out, int32_t max,
 int mts_batch_get_fields(mts_batch *b, int32_t box, double *host);
 int mts_batch_set_fields(mts_batch *b, int32_t box, const double *host);
 
-/* Tile shape of the batched launch: one ty in {4, 8, 12} for all boxes and
- * a tz[nbox] per box. */
+/* Tile shape of the batched launch: one ty in {4, 5, 8, 12} (and 13 in
+ * FP32) for all boxes and a tz[nbox] per box. */
 int mts_batch_set_tile(mts_batch *b, int32_t ty, const int32_t *tz);
 int mts_batch_set_streaming_stores(mts_batch *b, int32_t on);
 int mts_batch_get_streaming_stores(const mts_batch *b, int32_t *on);

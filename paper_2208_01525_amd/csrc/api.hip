@@ -1436,7 +1436,8 @@ int mts_batch_set_fields(mts_batch *b, int32_t box, const double *host) {
 
 int mts_batch_set_tile(mts_batch *b, int32_t ty, const int32_t *tz) {
     if (!b || !tz) return MTS_EINVAL;
-    if (!batch_tile_supported(TileShape{ty, 1})) return bfail(b, MTS_EINVAL, "ty must be 4, 8 or 12");
+    if (!batch_tile_supported(TileShape{ty, 1}, b->precision == MTS_FP64))
+        return bfail(b, MTS_EINVAL, "ty must be 4, 5, 8, 12 or (FP32) 13");
     for (size_t k = 0; k < b->box.size(); k++)
         if (tz[k] < 1) return bfail(b, MTS_EINVAL, "tz must be >= 1");
     BHIPCHK(b, hipStreamSynchronize(b->stream));
@@ -1495,7 +1496,7 @@ int mts_batch_timing_read(mts_batch *b, int64_t *steps, double *ms) {
 int mts_batch_autotune(mts_batch *b, int32_t steps, int32_t *ty_out, int32_t *tz_out, double *ms_out) {
     if (!b || steps < 1) return MTS_EINVAL;
     const size_t nbox = b->box.size();
-    const std::vector<int> tys = b->precision == MTS_FP64 ? std::vector<int>{4, 8} : std::vector<int>{4, 8, 12};
+    const std::vector<int> tys = b->precision == MTS_FP64 ? std::vector<int>{4, 5, 8} : std::vector<int>{4, 8, 12, 13};
     const int tzs[] = {8, 16, 32, 64};
     std::vector<int32_t> d(nbox);
     for (size_t k = 0; k < nbox; k++) {

@@ -88,7 +88,7 @@ struct TileShape {
     int32_t ty, tz;
 };
 bool tile_supported(TileShape ts, bool fp64);
-bool batch_tile_supported(TileShape ts);
+bool batch_tile_supported(TileShape ts, bool fp64);
 uint32_t tile_blocks(const Geom &g, TileShape ts);
 // With diag it also writes the phase arg(phi^n) of every site into
 // alpha[2][plane] (NaN where phi = 0), the winding kernel's input.

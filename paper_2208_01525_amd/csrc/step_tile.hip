@@ -408,7 +408,7 @@ bool tile_supported(TileShape ts, bool fp64) {
     return ok && ts.tz >= 1;
 }
 
-bool batch_tile_supported(TileShape ts) { return (ts.ty == 4 || ts.ty == 8 || ts.ty == 12) && ts.tz >= 1; }
+bool batch_tile_supported(TileShape ts, bool fp64) { return tile_supported(ts, fp64); }
 
 uint32_t tile_blocks(const Geom &g, TileShape ts) {
     const uint32_t ntx = (g.nx + 63) / 64, nty = (g.ny + ts.ty - 1) / ts.ty, ntz = (g.nz + ts.tz - 1) / ts.tz;
@@ -475,11 +475,16 @@ hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32
 #define MTS_BATCH_LAUNCH(TYV, D, N)                                                                                 \
     step_tile_batch_kernel<T, D, TYV, N><<<grid, dim3(64, TYV + 3, 1), 0, st>>>(boxes_dev, nbox, parity, mpin,   \
                                                                                  mpout, coef_dev, nblk)
+    // as for single boxes: no diagnostic variant for the shapes only plain steps use
 #define MTS_BATCH_CASE(TYV)                                           \
     case TYV:                                                         \
         if (diag) {                                                   \
-            if (nt) MTS_BATCH_LAUNCH(TYV, true, true);                \
-            else MTS_BATCH_LAUNCH(TYV, true, false);                  \
+            if constexpr (TYV == 13 || (TYV == 5 && sizeof(T) == 8)) {  \
+                return hipErrorNotSupported;                          \
+            } else {                                                  \
+                if (nt) MTS_BATCH_LAUNCH(TYV, true, true);            \
+                else MTS_BATCH_LAUNCH(TYV, true, false);              \
+            }                                                         \
         } else {                                                      \
             if (nt) MTS_BATCH_LAUNCH(TYV, false, true);               \
             else MTS_BATCH_LAUNCH(TYV, false, false);                 \
@@ -487,8 +492,18 @@ hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32
         return hipGetLastError();
     switch (ty) {
         MTS_BATCH_CASE(4)
+        MTS_BATCH_CASE(5)
         MTS_BATCH_CASE(8)
         MTS_BATCH_CASE(12)
+        case 13:
+            if constexpr (sizeof(T) == 4) {
+                if (diag) return hipErrorNotSupported;
+                if (nt) MTS_BATCH_LAUNCH(13, false, true);
+                else MTS_BATCH_LAUNCH(13, false, false);
+                return hipGetLastError();
+            } else {
+                return hipErrorInvalidValue;
+            }
         default: return hipErrorInvalidValue;
     }
 #undef MTS_BATCH_CASE

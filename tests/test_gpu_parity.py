@@ -337,18 +337,20 @@ def test_site_kernel_agrees_with_tiled_kernel(precision):
             lat.set_tile(13, 8)                 # its LDS does not fit in FP64
 
 
+@pytest.mark.parametrize("ty", [4, 5, 13])
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
-def test_batch_boxes_match_single_contexts(precision):
+def test_batch_boxes_match_single_contexts(precision, ty):
     """Uneven boxes (sizes, seeds, eras, s, a switch of s mid-run) in one batch give, box by
     box, the same fields bit for bit as single contexts with the same tile shape, and the
     same diagnostic records."""
+    if precision == "fp64" and ty == 13:
+        pytest.skip("13-row tiles are FP32 only")
     shapes = [(24, 16, 12), (70, 9, 5), (16, 16, 16), (33, 20, 7)]
     eras = [0.5, 2.0 / 3.0, 0.5, 2.0 / 3.0]
     s_b, s_a, sw = [0.0, 1.0, 0.0, 1.0], [1.0, 1.0, 1.0, 0.0], [1.8, 99.0, 1.45, 1.2]
     kw = dict(precision=precision, diag_every=3)
     params = [P.make_params(*sh, eta_ref=5.0 + k, **kw) for k, sh in enumerate(shapes)]
     bt = P.Batch(params)
-    ty = 4
     bt.set_tile(ty, [32, 2, 5, 3])
     bt.init_fields([1000 + k for k in range(4)])
     n = 10

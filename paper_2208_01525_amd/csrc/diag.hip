@@ -25,7 +25,12 @@ namespace mts {
 
 namespace {
 
-constexpr int DX = 64, DY = 4, DZ = 4;   // wind/Gauss blocks: 64 x 4 columns, DZ planes per thread
+// Wind/Gauss blocks: 64 x 4 columns, DZ planes per thread.  The blocks form a
+// 1-D grid dealt to the XCDs in contiguous runs (x fastest, then y, then z),
+// so the neighbouring columns and rows a block reads are fetched by blocks on
+// the same XCD at about the same time and come from its L2, not from HBM;
+// 16 planes per block keep the re-read z-halo plane to a sixteenth.
+constexpr int DX = 64, DY = 4, DZ = 16;
 
 template <typename T>
 struct Guard;
@@ -104,15 +109,18 @@ template <typename T>
 __global__ __launch_bounds__(DX *DY) void wind_gauss_kernel(Geom g, Fields<T> f, Moms<T> mom, const T *alpha, T h,
                                                             double g_p, double g_q, uint8_t *wabs, uint32_t plane,
                                                             int8_t *signed_out, Partials part) {
-    const int x = blockIdx.x * DX + threadIdx.x;
-    const int y = blockIdx.y * DY + threadIdx.y;
+    const uint32_t gx = (g.nx + DX - 1) / DX, gy = (g.ny + DY - 1) / DY;
+    const uint32_t blk = xcd_order(blockIdx.x, gridDim.x);
+    const uint32_t bx = blk % gx, by = (blk / gx) % gy, bz = blk / (gx * gy);
+    const int x = bx * DX + threadIdx.x;
+    const int y = by * DY + threadIdx.y;
     double acc[6] = {0, 0, 0, 0, 0, 0};   // gauss_abs p,q; gauss_scale p,q; wind p,q
     if (x < g.nx && y < g.ny) {
         const int xp = wrap1(x + 1, g.nx), xm = wrap1(x - 1, g.nx);
         const int yp = wrap1(y + 1, g.ny), ym = wrap1(y - 1, g.ny);
         const T inv2pi = T(0.5) / Pi<T>::v;
-        const int z1 = min((int)(blockIdx.z + 1) * DZ, g.nz);
-        for (int z = blockIdx.z * DZ; z < z1; z++) {
+        const int z1 = min((int)(bz + 1) * DZ, g.nz);
+        for (int z = bz * DZ; z < z1; z++) {
             const int zp = wrap1(z + 1, g.nz), zm = wrap1(z - 1, g.nz);
             const uint32_t nx = g.nx, nxy = g.nxy;
             const uint32_t s = x + nx * y + nxy * z;
@@ -167,17 +175,14 @@ __global__ __launch_bounds__(DX *DY) void wind_gauss_kernel(Geom g, Fields<T> f,
             }
         }
     }
-    if (!signed_out) {
-        const uint32_t blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-        block_sum_store<6, (DX * DY) / 64>(acc, part, SL_GAUSS_ABS_P, blk);
-    }
+    if (!signed_out) block_sum_store<6, (DX * DY) / 64>(acc, part, SL_GAUSS_ABS_P, blk);
 }
 
 template <typename T>
 hipError_t launch_wind_gauss(const Geom &g, Fields<T> f, Moms<T> mom, const T *alpha, T h, const double gcoef[2],
                              uint8_t *wabs, uint32_t plane, int8_t *signed_out, Partials part, hipStream_t st) {
     dim3 block(DX, DY, 1);
-    dim3 grid((g.nx + DX - 1) / DX, (g.ny + DY - 1) / DY, (g.nz + DZ - 1) / DZ);
+    dim3 grid(wind_blocks(g), 1, 1);
     wind_gauss_kernel<T><<<grid, block, 0, st>>>(g, f, mom, alpha, h, gcoef[0], gcoef[1], wabs, plane, signed_out,
                                                  part);
     return hipGetLastError();
@@ -192,15 +197,19 @@ uint32_t overlap_words(const Geom &g) { return (uint32_t)(g.nx / 64) * (uint32_t
 // Cell value = sum of |W| over the six faces of the cell [x, x+1]^3; with
 // `bits`, also the 64-cell occupancy words of each sector.  A block holds
 // 64 x 4 columns and walks CZ planes, carrying the packed |W| byte of the
-// next plane (the upper z face) over to the following iteration.
+// next plane (the upper z face) over to the following iteration.  Blocks
+// are dealt to the XCDs in contiguous runs, as for the wind/Gauss kernel.
 constexpr int CZ = 16;
 
 __global__ __launch_bounds__(256) void cells_kernel(Geom g, const uint8_t *wabs, uint8_t *cells, uint64_t *bits,
                                                     uint32_t plane, uint32_t nwords) {
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
+    const uint32_t gx = (g.nx + 63) / 64, gy = (g.ny + 3) / 4;
+    const uint32_t blk = xcd_order(blockIdx.x, gridDim.x);
+    const uint32_t bx = blk % gx, by = (blk / gx) % gy, bz = blk / (gx * gy);
+    const int x = bx * 64 + threadIdx.x;
+    const int y = by * 4 + threadIdx.y;
     const bool in = x < g.nx && y < g.ny;
-    const int z0 = blockIdx.z * CZ, z1 = min(z0 + CZ, g.nz);
+    const int z0 = bz * CZ, z1 = min(z0 + CZ, g.nz);
     const uint32_t col = in ? (uint32_t)x + (uint32_t)g.nx * (uint32_t)y : 0u;
     const uint32_t colx = in ? (uint32_t)wrap1(x + 1, g.nx) + (uint32_t)g.nx * (uint32_t)y : 0u;
     const uint32_t coly = in ? (uint32_t)x + (uint32_t)g.nx * (uint32_t)wrap1(y + 1, g.ny) : 0u;
@@ -237,7 +246,7 @@ __global__ __launch_bounds__(256) void cells_kernel(Geom g, const uint8_t *wabs,
 hipError_t launch_cells(const Geom &g, const uint8_t *wabs, uint8_t *cells, uint64_t *bits, uint32_t plane,
                         hipStream_t st) {
     dim3 block(64, 4, 1);
-    dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, (g.nz + CZ - 1) / CZ);
+    dim3 grid((unsigned)((g.nx + 63) / 64) * (unsigned)((g.ny + 3) / 4) * (unsigned)((g.nz + CZ - 1) / CZ), 1, 1);
     cells_kernel<<<grid, block, 0, st>>>(g, wabs, cells, overlap_uses_bits(g) ? bits : nullptr, plane,
                                          overlap_words(g));
     return hipGetLastError();

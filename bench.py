@@ -44,17 +44,17 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(n, precision, tile, nt, pf, pp=False):
+def measured_traffic(n, precision, tile, nt, pf, pp=False, xcd=True):
     """HBM bytes per launch of the update kernel from the committed rocprofv3
     counter summary, if it was taken on this kernel source, tile shape, store
-    mode, load pipeline and workload; else None."""
+    mode, load pipeline, momentum mode, tile order and workload; else None."""
     if n != 512 or precision != "fp32" or not os.path.exists(TRAFFIC_FILE):
         return None
     lines = [l.strip() for l in open(TRAFFIC_FILE) if l.strip() and not l.startswith("#")]
     head = dict(l.split("=", 1) for l in lines if " " not in l and "=" in l)
     if head.get("source_sha256") != kernel_source_hash():
         return None
-    want = f"{tile[0]},{tile[1]},{int(nt)},{int(pf)}" + (",1" if pp else "")
+    want = f"{tile[0]},{tile[1]},{int(nt)},{int(pf)},{int(pp)},{int(xcd)}"
     for l in lines:
         kv = dict(f.split("=", 1) for f in l.split() if "=" in f)
         if kv.get("config") == want:
@@ -75,6 +75,8 @@ def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0
             lat.set_prefetch(bool(tile[3]))
         if len(tile) > 4:
             lat.set_momentum_pingpong(bool(tile[4]))
+        if len(tile) > 5:
+            lat.set_tile_order(bool(tile[5]))
     else:
         tuned = lat.autotune(4)      # times every tile shape on this machine (leaves seed-0 fields)
     if time_blocking is not None:
@@ -114,7 +116,7 @@ def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(n, precision, lat.get_tile(), lat.get_streaming_stores(),
-                                                lat.get_prefetch(), lat.get_momentum_pingpong())
+                                                lat.get_prefetch(), lat.get_momentum_pingpong(), lat.get_tile_order())
                      if per_launch == 1 else None,
                      "algorithmic_bytes": BYTES_PER_SITE[precision] * sites,
                      "box_ceiling": {**{k: round(v, 1) for k, v in ceiling.items()},
@@ -123,6 +125,7 @@ def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0
         "tile": lat.get_tile(),
         "streaming_stores": lat.get_streaming_stores(),
         "prefetch": lat.get_prefetch(),
+        "tile_order": "xcd_runs" if lat.get_tile_order() else "round_robin",
         "momentum_pingpong": lat.get_momentum_pingpong(),
         "time_blocking": {"steps_per_sweep": tblock[0], "tile": list(tblock[1:])},
         "autotune_ms_per_step": tuned[2] if tuned else None,
@@ -163,7 +166,8 @@ def run_batch(P, torch, steps, small=48, big=16, tune_steps=3):
     out = {"value": sites * steps / wall, "unit": "site-updates/s", "boxes": f"{small}x128^3 + {big}x256^3",
            "sites": sites, "steps": steps, "ms_per_step": 1e3 * wall / steps, "graph_ms": tm["ms"],
            "tile": [ty, tz], "streaming_stores": bt.get_streaming_stores(),
-           "momentum_pingpong": bt.get_momentum_pingpong(), "autotune_ms_per_step": tune_ms,
+           "momentum_pingpong": bt.get_momentum_pingpong(),
+           "tile_order": "xcd_runs" if bt.get_tile_order() else "round_robin", "autotune_ms_per_step": tune_ms,
            "records_per_box": min(nrec),
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -230,8 +234,9 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only time a plain copy (counter calibration)")
     ap.add_argument("--source-hash", action="store_true", help="print the update kernel's source hash")
     ap.add_argument("--tile", type=str, default=None,
-                    help="ty,tz[,nt[,pf[,pp]]] of the update kernel (0,1: per-site kernel; nt 1/0: streaming or "
-                         "plain stores; pf 1/0: deeper load pipeline or not; pp 1/0: momentum ping-pong)")
+                    help="ty,tz[,nt[,pf[,pp[,xcd]]]] of the update kernel (0,1: per-site kernel; nt 1/0: streaming "
+                         "or plain stores; pf 1/0: deeper load pipeline or not; pp 1/0: momentum ping-pong; xcd "
+                         "1/0: tiles in contiguous runs per XCD or round-robin)")
     ap.add_argument("--time-blocking", type=str, default=None,
                     help="steps,ty,tz: steps per sweep (1, or 2: the two-step kernel with 64 x ty x tz tiles), FP32 leg")
     args = ap.parse_args()
@@ -291,12 +296,14 @@ def main():
         "streaming_stores": fp32["streaming_stores"],
         "prefetch": fp32["prefetch"],
         "momentum_pingpong": fp32["momentum_pingpong"],
+        "tile_order": fp32["tile_order"],
         "time_blocking": fp32["time_blocking"],
         "diag_step_kernel_ms": fp32["diag_step_kernel_ms"],
         "diag_post_ms": fp32["diag_post_ms"],
         "fp64": {"value": fp64["value"], "unit": "site-updates/s", "steps": args.fp64_steps,
                  "ms_per_step": fp64["ms_per_step"], "kernel_ms": fp64["kernel_ms"], "tile": fp64["tile"],
-                 "streaming_stores": fp64["streaming_stores"], "roofline": fp64["roofline"]} if fp64 else None,
+                 "streaming_stores": fp64["streaming_stores"], "tile_order": fp64["tile_order"],
+                 "roofline": fp64["roofline"]} if fp64 else None,
         "batch": batch,
         "last_record": fp32["last_record"],
     }

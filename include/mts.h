@@ -239,6 +239,17 @@ int mts_get_streaming_stores(const mts_ctx *ctx, int32_t *on);
 int mts_set_momentum_pingpong(mts_ctx *ctx, int32_t on);
 int mts_get_momentum_pingpong(const mts_ctx *ctx, int32_t *on);
 
+/* Order in which the tiled kernel's workgroups take their tiles.  With
+ * xcd_runs = 1 (the default) the tiles are dealt to the GPU's 8 XCDs in
+ * contiguous runs (x fastest, then y, then z), so that neighbouring tiles
+ * share one L2; with 0 workgroup b takes tile b and the hardware's
+ * round-robin dispatch spreads neighbouring tiles over all XCDs, which keeps
+ * every XCD streaming through the same region of HBM.  Which is faster
+ * depends on the box; results are bitwise identical; the autotuner tries
+ * both.  Synchronises the stream.  Update of Sec. III. */
+int mts_set_tile_order(mts_ctx *ctx, int32_t xcd_runs);
+int mts_get_tile_order(const mts_ctx *ctx, int32_t *xcd_runs);
+
 /* Deeper load pipeline in the tiled update's plain steps: on (1) loads each
  * plane's fields two planes before they are used (more registers per
  * thread, fewer stalls on HBM); off (0, the default) one plane before.
@@ -267,7 +278,8 @@ int mts_get_time_blocking(const mts_ctx *ctx, int32_t *steps, int32_t *ty, int32
  * without streaming stores) on this
  * box with HIP events, keep the fastest, and report it (and its ms per
  * step), each with and without the deeper load pipeline
- * (mts_set_prefetch), and the fastest of them with momentum ping-pong.
+ * (mts_set_prefetch), and the fastest of them with momentum ping-pong
+ * and then with the other tile order (mts_set_tile_order).
  * In FP32 it then times the two-step kernel (ty in {3, 7} by the
  * same tz and store modes, over an even number of steps) and switches
  * time blocking on if that is faster per step (mts_get_time_blocking tells
@@ -355,13 +367,18 @@ int mts_batch_get_streaming_stores(const mts_batch *b, int32_t *on);
 int mts_batch_set_momentum_pingpong(mts_batch *b, int32_t on);
 int mts_batch_get_momentum_pingpong(const mts_batch *b, int32_t *on);
 
+/* Tile order of the batched launch, as mts_set_tile_order (over the
+ * batch's whole grid of tiles); the batch autotuner tries both. */
+int mts_batch_set_tile_order(mts_batch *b, int32_t xcd_runs);
+int mts_batch_get_tile_order(const mts_batch *b, int32_t *xcd_runs);
+
 /* Summed HIP-event time (ms) of the graph launches and the steps they ran
  * since the last read; synchronises. */
 int mts_batch_timing_read(mts_batch *b, int64_t *steps, double *ms);
 
 /* Autotuner of the batched launch (one ty and one tz for all boxes, streaming
- * stores, then momentum ping-pong on the best of those), as mts_autotune;
- * overwrites every box. */
+ * stores, then momentum ping-pong and the tile order on the best of those),
+ * as mts_autotune; overwrites every box. */
 int mts_batch_autotune(mts_batch *b, int32_t steps, int32_t *ty, int32_t *tz, double *ms_per_step);
 
 const char *mts_batch_last_error(const mts_batch *b);

@@ -43,6 +43,7 @@ struct mts_ctx {
     bool nt = true;              // streaming stores in the tiled update
     bool pf = false;             // loads one plane ahead in the tiled update (plain steps)
     bool mpp = false;            // tiled steps write the momenta to the other momentum copy
+    bool xcd = true;             // tiles dealt to the XCDs in contiguous runs (else round-robin)
     int tblock = 1;              // leapfrog steps per sweep through HBM (1, or 2: two-step kernel)
     TileShape tile2{7, 32};      // tile of the two-step kernel
     void *mom2 = nullptr;        // second momentum copy (10 planes), allocated for two-step sweeps
@@ -336,7 +337,7 @@ int do_step(mts_ctx *c, int32_t n, double eta, double era_m, double s) {
                                : launch_step_tile<T>(c->g, in, out, mom, mom_out, coef, diag, part,
                                                      diag ? diag_tile(c) : c->tile,
                                                      static_cast<T *>(c->alpha), (uint32_t)c->plane, c->nt,
-                                                     c->pf, c->stream);
+                                                     c->pf, c->xcd, c->stream);
             if (e != hipSuccess) return hipfail(c, e, "step kernel launch");
         }
         if (pp) c->mcur = 1 - c->mcur;   // the diagnostic kernels below read the new momenta
@@ -816,6 +817,19 @@ int mts_get_momentum_pingpong(const mts_ctx *c, int32_t *on) {
     return MTS_OK;
 }
 
+int mts_set_tile_order(mts_ctx *c, int32_t xcd_runs) {
+    if (!c) return MTS_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->xcd = xcd_runs != 0;
+    return MTS_OK;
+}
+
+int mts_get_tile_order(const mts_ctx *c, int32_t *xcd_runs) {
+    if (!c || !xcd_runs) return MTS_EINVAL;
+    *xcd_runs = c->xcd ? 1 : 0;
+    return MTS_OK;
+}
+
 int mts_set_prefetch(mts_ctx *c, int32_t on) {
     if (!c) return MTS_EINVAL;
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -979,6 +993,23 @@ int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, do
         c->mpp = false;
         if (rc == MTS_OK) c->err.clear();
     }
+    // and with the other tile order (contiguous runs per XCD or round-robin)
+    bool pick_xcd = c->xcd;
+    if (rc == MTS_OK) {
+        c->mpp = pick_mpp;
+        c->xcd = !pick_xcd;
+        float ms = 0;
+        if ((rc = mts_step(c, 1, 1.0, 0.5, 1.0)) == MTS_OK && hip(hipEventRecord(e0, c->stream), "hipEventRecord") &&
+            (rc = mts_step(c, steps, 1.3, 0.5, 1.0)) == MTS_OK &&
+            hip(hipEventRecord(e1, c->stream), "hipEventRecord") &&
+            hip(hipEventSynchronize(e1), "hipEventSynchronize") &&
+            hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime") && ms < best) {
+            best = ms;
+            pick_xcd = !pick_xcd;
+        }
+        c->xcd = pick_xcd;
+        c->mpp = false;
+    }
 
     // two steps per sweep (FP32), timed over an even number of steps, per step
     double best_ps = best / steps;
@@ -1105,6 +1136,7 @@ struct mts_batch {
     uint32_t nblk_diag = 0;
     bool nt = true;                  // streaming stores in the tiled update
     bool mpp = false;                // plain tiled steps write the momenta to the other copy
+    bool xcd = true;                 // tiles dealt to the XCDs in contiguous runs (else round-robin)
     void *coef_dev = nullptr;        // StepCoef<T>[n][nbox]
     size_t coef_cap = 0;             // bytes
     int32_t ty = 8;
@@ -1276,7 +1308,7 @@ int batch_step_t(mts_batch *b, int32_t n, const double *eta0, const double *era_
             err = launch_step_tile_batch<T>(static_cast<const BatchBox<T> *>(diag ? b->boxes_diag_dev : b->boxes_dev),
                                             (int)nbox, diag ? b->nblk_diag : b->nblk, c0->cur, mpin, mpout,
                                             static_cast<const StepCoef<T> *>(b->coef_dev) + (size_t)j * nbox, diag,
-                                            diag ? b->ty_diag : b->ty, b->nt, b->stream);
+                                            diag ? b->ty_diag : b->ty, b->nt, b->xcd, b->stream);
             if (mpout != mpin)
                 for (mts_ctx *c : b->box) c->mcur = mpout;
         }
@@ -1482,6 +1514,19 @@ int mts_batch_get_momentum_pingpong(const mts_batch *b, int32_t *on) {
     return MTS_OK;
 }
 
+int mts_batch_set_tile_order(mts_batch *b, int32_t xcd_runs) {
+    if (!b) return MTS_EINVAL;
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    b->xcd = xcd_runs != 0;
+    return MTS_OK;
+}
+
+int mts_batch_get_tile_order(const mts_batch *b, int32_t *xcd_runs) {
+    if (!b || !xcd_runs) return MTS_EINVAL;
+    *xcd_runs = b->xcd ? 1 : 0;
+    return MTS_OK;
+}
+
 int mts_batch_timing_read(mts_batch *b, int64_t *steps, double *ms) {
     if (!b) return MTS_EINVAL;
     BHIPCHK(b, hipStreamSynchronize(b->stream));
@@ -1555,6 +1600,22 @@ int mts_batch_autotune(mts_batch *b, int32_t steps, int32_t *ty_out, int32_t *tz
         }
         b->mpp = false;
         if (rc == MTS_OK) b->err.clear();
+    }
+    // and with the other tile order (contiguous runs per XCD or round-robin)
+    if (rc == MTS_OK) {
+        const bool cur = b->xcd;
+        b->mpp = pick_mpp;
+        b->xcd = !cur;
+        int64_t ns = 0;
+        double ms = 0;
+        if ((rc = mts_batch_step(b, 1, eta.data(), era.data(), sv.data(), nullptr, nullptr)) == MTS_OK &&
+            (rc = mts_batch_timing_read(b, &ns, &ms)) == MTS_OK &&
+            (rc = mts_batch_step(b, steps, eta.data(), era.data(), sv.data(), nullptr, nullptr)) == MTS_OK &&
+            (rc = mts_batch_timing_read(b, &ns, &ms)) == MTS_OK && ms < best)
+            best = ms;
+        else
+            b->xcd = cur;
+        b->mpp = false;
     }
     for (size_t k = 0; k < nbox; k++) b->box[k]->p.diag_every = d[k];
     if (rc != MTS_OK) return rc;

@@ -107,11 +107,14 @@ hipError_t launch_cool_tile(const Geom &g, Fields<T> in, Fields<T> out, const St
 // nt selects streaming (non-temporal) stores for the outputs; pf loads the
 // fields of plain steps one plane further ahead (FP32 diagnostic steps always do).
 // Momenta are read from `mom` and written to `mom_out` (the same copy: in
-// place).
+// place).  xcd deals the tiles to the XCDs in contiguous runs (block b of
+// XCD b mod 8 takes that XCD's next tile in x, y, z order); without it block
+// b takes tile b, the hardware's round-robin order.  Results do not depend
+// on it.
 template <typename T>
 hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, Moms<T> mom_out,
                             const StepCoef<T> &c, bool diag, Partials part, TileShape ts, T *alpha, uint32_t plane,
-                            bool nt, bool pf, hipStream_t st);
+                            bool nt, bool pf, bool xcd, hipStream_t st);
 
 // Two steps in one sweep (temporal blocking, FP32): reads fields n from
 // `in` and momenta n - 1/2 from `min_`, writes fields n + 2 to `out` and
@@ -139,7 +142,8 @@ struct BatchBox {
 // `mpout` (equal: in place).
 template <typename T>
 hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32_t nblk, int parity, int mpin,
-                                  int mpout, const StepCoef<T> *coef_dev, bool diag, int ty, bool nt, hipStream_t st);
+                                  int mpout, const StepCoef<T> *coef_dev, bool diag, int ty, bool nt, bool xcd,
+                                  hipStream_t st);
 
 // Phase alpha = arg(phi) of every site and sector into alpha[2][plane]
 // (NaN where phi = 0), input of the winding kernel.

@@ -311,9 +311,10 @@ template <typename T, bool DIAG, int TY, bool NT, int PF>
 __global__ __launch_bounds__(64 * (TY + 3)) void step_tile_kernel(Geom g, Fields<T> in, Fields<T> out, Moms<T> mom,
                                                                   Moms<T> mom_out,
                                                                   StepCoef<T> c, Partials part, int TZ, int ntx,
-                                                                  int nty, int ntz, T *alpha, uint32_t plane) {
+                                                                  int nty, int ntz, T *alpha, uint32_t plane,
+                                                                  int xcd) {
     __shared__ Lds<T, TY> L;
-    const uint32_t t = xcd_order(blockIdx.x, (uint32_t)(ntx * nty * ntz));
+    const uint32_t t = xcd ? xcd_order(blockIdx.x, (uint32_t)(ntx * nty * ntz)) : blockIdx.x;
     const int tx = t % ntx, ty_ = (t / ntx) % nty, tz = t / (ntx * nty);
     double acc[6] = {0, 0, 0, 0, 0, 0};
     tile_step<T, DIAG, TY, NT, false, PF>(g, in, out, mom, mom_out, c, tx * 64, ty_ * TY, tz * TZ, TZ, L, acc, alpha,
@@ -327,9 +328,10 @@ __global__ __launch_bounds__(64 * (TY + 3)) void step_tile_kernel(Geom g, Fields
 template <typename T, bool DIAG, int TY, bool NT>
 __global__ __launch_bounds__(64 * (TY + 3)) void step_tile_batch_kernel(const BatchBox<T> *boxes, int nbox,
                                                                         int parity, int mpin, int mpout,
-                                                                        const StepCoef<T> *coef, uint32_t nblk) {
+                                                                        const StepCoef<T> *coef, uint32_t nblk,
+                                                                        int xcd) {
     __shared__ Lds<T, TY> L;
-    const uint32_t t = xcd_order(blockIdx.x, nblk);
+    const uint32_t t = xcd ? xcd_order(blockIdx.x, nblk) : blockIdx.x;
     int lo = 0, hi = nbox - 1;             // last box with blk0 <= t
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -418,13 +420,14 @@ uint32_t tile_blocks(const Geom &g, TileShape ts) {
 template <typename T, int TY>
 static hipError_t launch_ty(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, Moms<T> mom_out,
                             const StepCoef<T> &c, bool diag,
-                            Partials part, int tz, T *alpha, uint32_t plane, bool nt, bool pf, hipStream_t st) {
+                            Partials part, int tz, T *alpha, uint32_t plane, bool nt, bool pf, bool xcd,
+                            hipStream_t st) {
     const int ntx = (g.nx + 63) / 64, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + tz - 1) / tz;
     dim3 block(64, TY + 3, 1);
     dim3 grid((unsigned)(ntx * nty * ntz), 1, 1);
 #define MTS_TILE_LAUNCH(D, N, F) \
     step_tile_kernel<T, D, TY, N, F><<<grid, block, 0, st>>>(g, in, out, mom, mom_out, c, part, tz, ntx, nty, ntz, \
-                                                             alpha, plane)
+                                                             alpha, plane, xcd ? 1 : 0)
     if (diag) {
         // FP32 diagnostic steps always load the fields one plane further
         // ahead: at the row counts they run with it costs no occupancy and
@@ -453,15 +456,16 @@ static hipError_t launch_ty(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> 
 template <typename T>
 hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, Moms<T> mom_out,
                             const StepCoef<T> &c, bool diag,
-                            Partials part, TileShape ts, T *alpha, uint32_t plane, bool nt, bool pf, hipStream_t st) {
+                            Partials part, TileShape ts, T *alpha, uint32_t plane, bool nt, bool pf, bool xcd,
+                            hipStream_t st) {
     switch (ts.ty) {
-        case 4: return launch_ty<T, 4>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, st);
-        case 8: return launch_ty<T, 8>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, st);
-        case 5: return launch_ty<T, 5>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, st);
-        case 12: return launch_ty<T, 12>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, st);
+        case 4: return launch_ty<T, 4>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, xcd, st);
+        case 8: return launch_ty<T, 8>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, xcd, st);
+        case 5: return launch_ty<T, 5>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, xcd, st);
+        case 12: return launch_ty<T, 12>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, xcd, st);
         case 13:
             if constexpr (sizeof(T) == 4)
-                return launch_ty<T, 13>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, st);
+                return launch_ty<T, 13>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, xcd, st);
             else
                 return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
@@ -470,11 +474,12 @@ hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> 
 
 template <typename T>
 hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32_t nblk, int parity, int mpin,
-                                  int mpout, const StepCoef<T> *coef_dev, bool diag, int ty, bool nt, hipStream_t st) {
+                                  int mpout, const StepCoef<T> *coef_dev, bool diag, int ty, bool nt, bool xcd,
+                                  hipStream_t st) {
     dim3 grid(nblk, 1, 1);
 #define MTS_BATCH_LAUNCH(TYV, D, N)                                                                                 \
     step_tile_batch_kernel<T, D, TYV, N><<<grid, dim3(64, TYV + 3, 1), 0, st>>>(boxes_dev, nbox, parity, mpin,   \
-                                                                                 mpout, coef_dev, nblk)
+                                                                                 mpout, coef_dev, nblk, xcd ? 1 : 0)
     // as for single boxes: no diagnostic variant for the shapes only plain steps use
 #define MTS_BATCH_CASE(TYV)                                           \
     case TYV:                                                         \
@@ -511,15 +516,15 @@ hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32
 }
 
 template hipError_t launch_step_tile_batch<float>(const BatchBox<float> *, int, uint32_t, int, int, int,
-                                                  const StepCoef<float> *, bool, int, bool, hipStream_t);
+                                                  const StepCoef<float> *, bool, int, bool, bool, hipStream_t);
 template hipError_t launch_step_tile_batch<double>(const BatchBox<double> *, int, uint32_t, int, int, int,
-                                                   const StepCoef<double> *, bool, int, bool, hipStream_t);
+                                                   const StepCoef<double> *, bool, int, bool, bool, hipStream_t);
 
 template hipError_t launch_step_tile<float>(const Geom &, Fields<float>, Fields<float>, Moms<float>, Moms<float>,
                                             const StepCoef<float> &, bool, Partials, TileShape, float *, uint32_t,
-                                            bool, bool, hipStream_t);
+                                            bool, bool, bool, hipStream_t);
 template hipError_t launch_step_tile<double>(const Geom &, Fields<double>, Fields<double>, Moms<double>, Moms<double>,
                                              const StepCoef<double> &, bool, Partials, TileShape, double *, uint32_t,
-                                             bool, bool, hipStream_t);
+                                             bool, bool, bool, hipStream_t);
 
 }  // namespace mts

@@ -19,11 +19,11 @@ MTS_FP32, MTS_FP64 = 1, 2
 
 EXPORTS = ("mts_state_bytes", "mts_create", "mts_destroy", "mts_init_fields", "mts_step", "mts_cool", "mts_diagnostics",
            "mts_get_fields", "mts_set_fields", "mts_get_windings", "mts_get_cells", "mts_get_sites", "mts_segments", "mts_set_tile", "mts_get_tile", "mts_set_streaming_stores", "mts_bandwidth_probe", "mts_get_streaming_stores", "mts_autotune", "mts_timing_enable",
-           "mts_timing_read", "mts_set_time_blocking", "mts_get_time_blocking", "mts_set_prefetch", "mts_get_prefetch", "mts_set_momentum_pingpong", "mts_get_momentum_pingpong", "mts_last_error", "mts_strerror",
+           "mts_timing_read", "mts_set_time_blocking", "mts_get_time_blocking", "mts_set_prefetch", "mts_get_prefetch", "mts_set_momentum_pingpong", "mts_get_momentum_pingpong", "mts_set_tile_order", "mts_get_tile_order", "mts_last_error", "mts_strerror",
            "mts_batch_state_bytes", "mts_batch_create", "mts_batch_destroy", "mts_batch_size",
            "mts_batch_init_fields", "mts_batch_step", "mts_batch_diagnostics", "mts_batch_get_fields",
            "mts_batch_set_fields", "mts_batch_set_tile", "mts_batch_set_streaming_stores", "mts_batch_get_streaming_stores", "mts_batch_set_momentum_pingpong",
-           "mts_batch_get_momentum_pingpong", "mts_batch_timing_read", "mts_batch_autotune",
+           "mts_batch_get_momentum_pingpong", "mts_batch_set_tile_order", "mts_batch_get_tile_order", "mts_batch_timing_read", "mts_batch_autotune",
            "mts_batch_last_error")
 
 
@@ -115,6 +115,8 @@ def load():
     L.mts_batch_get_streaming_stores.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.mts_batch_set_momentum_pingpong.argtypes = [vp, ctypes.c_int32]
     L.mts_batch_get_momentum_pingpong.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.mts_batch_set_tile_order.argtypes = [vp, ctypes.c_int32]
+    L.mts_batch_get_tile_order.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.mts_get_tile.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     i32p = ctypes.POINTER(ctypes.c_int32)
     L.mts_autotune.argtypes = [vp, ctypes.c_int32, i32p, i32p, ctypes.POINTER(ctypes.c_double)]
@@ -127,6 +129,8 @@ def load():
     L.mts_set_prefetch.argtypes = [vp, ctypes.c_int32]
     L.mts_set_momentum_pingpong.argtypes = [vp, ctypes.c_int32]
     L.mts_get_momentum_pingpong.argtypes = [vp, i32p]
+    L.mts_set_tile_order.argtypes = [vp, ctypes.c_int32]
+    L.mts_get_tile_order.argtypes = [vp, i32p]
     L.mts_get_prefetch.argtypes = [vp, i32p]
     L.mts_last_error.argtypes = [vp]
     L.mts_last_error.restype = ctypes.c_char_p
@@ -326,6 +330,14 @@ class Lattice:
         self._check(self.L.mts_get_momentum_pingpong(self.ctx, ctypes.byref(v)))
         return bool(v.value)
 
+    def set_tile_order(self, xcd_runs):
+        self._check(self.L.mts_set_tile_order(self.ctx, 1 if xcd_runs else 0))
+
+    def get_tile_order(self):
+        v = ctypes.c_int32()
+        self._check(self.L.mts_get_tile_order(self.ctx, ctypes.byref(v)))
+        return bool(v.value)
+
     def set_prefetch(self, on):
         self._check(self.L.mts_set_prefetch(self.ctx, 1 if on else 0))
 
@@ -432,6 +444,14 @@ class Batch:
 
     def set_momentum_pingpong(self, on):
         self._check(self.L.mts_batch_set_momentum_pingpong(self.b, 1 if on else 0))
+
+    def set_tile_order(self, xcd_runs):
+        self._check(self.L.mts_batch_set_tile_order(self.b, 1 if xcd_runs else 0))
+
+    def get_tile_order(self):
+        v = ctypes.c_int32()
+        self._check(self.L.mts_batch_get_tile_order(self.b, ctypes.byref(v)))
+        return bool(v.value)
 
     def get_momentum_pingpong(self):
         v = ctypes.c_int32()

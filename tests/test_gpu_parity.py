@@ -260,31 +260,33 @@ def test_small_workload_full_run(precision):
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_tile_shapes_bitwise_identical(precision):
     """Every tile shape of the z-marching kernel, with streaming or plain stores, with or
-    without the deeper load pipeline and with the momenta rewritten in place or written to
-    the second copy, gives the same fields bit for bit (on a box with ragged tiles in every
+    without the deeper load pipeline, with the momenta rewritten in place or written to
+    the second copy and in either tile order, gives the same fields bit for bit (on a box with ragged tiles in every
     direction; 12 steps with diagnostics every 4, so the momenta end in either copy)."""
     nx, ny, nz = 70, 21, 13
     st = rounded(I.random_full(nx, ny, nz, 11, link=0.5, mom=0.5), precision)
     ref = None
-    shapes = [(8, 32, True, False, False), (4, 1, False, False, True), (12, 5, True, True, False),
-              (4, 7, True, True, True), (8, 13, False, True, False), (8, 32, False, False, True),
-              (12, 64, True, True, True), (8, 2, True, True, False), (5, 3, True, False, True),
-              (5, 32, False, True, False)]
+    shapes = [(8, 32, True, False, False, True), (4, 1, False, False, True, False),
+              (12, 5, True, True, False, True), (4, 7, True, True, True, True), (8, 13, False, True, False, False),
+              (8, 32, False, False, True, True), (12, 64, True, True, True, False), (8, 2, True, True, False, True),
+              (5, 3, True, False, True, False), (5, 32, False, True, False, True)]
     if precision == "fp32":
-        shapes += [(13, 6, True, False, True), (13, 64, False, True, False)]
-    for ty, tz, nt, pf, pp in shapes:
+        shapes += [(13, 6, True, False, True, True), (13, 64, False, True, False, False)]
+    for ty, tz, nt, pf, pp, xcd in shapes:
         lat = lattice(nx, ny, nz, precision, eta_ref=9.0, diag_every=4)
         lat.set_tile(ty, tz)
         lat.set_streaming_stores(nt)
         lat.set_prefetch(pf)
         lat.set_momentum_pingpong(pp)
+        lat.set_tile_order(xcd)
+        assert lat.get_tile_order() == xcd
         lat.set_fields(st)
         lat.step(12, 1.0, 0.5, 1.0)
         got = lat.get_fields()
         recs = lat.diagnostics()
         if ref is None:
             ref, rrec = got, recs
-        assert np.array_equal(got, ref), (ty, tz, nt, pf, pp)
+        assert np.array_equal(got, ref), (ty, tz, nt, pf, pp, xcd)
         for a, b in zip(recs, rrec):
             assert a["sum_energy"] == pytest.approx(b["sum_energy"], rel=1e-13)
             assert a["wind_abs"] == b["wind_abs"] and a["pq_count2"] == b["pq_count2"]
@@ -386,8 +388,9 @@ def test_batch_boxes_match_single_contexts(precision, ty):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_batch_momentum_pingpong_bitwise(precision):
-    """Ensemble steps with the momenta written to the other copy give the same fields and
-    diagnostic records bit for bit as in-place steps; plain and diagnostic steps alternate
+    """Ensemble steps with the momenta written to the other copy (and the tiles in the
+    hardware's round-robin order) give the same fields and diagnostic records bit for bit
+    as in-place steps in XCD runs; plain and diagnostic steps alternate
     (diagnostics every 3), the step count is odd, and a checkpoint taken while the momenta
     live in the second copy continues bit for bit in a fresh in-place batch."""
     shapes = [(24, 16, 12), (70, 9, 5), (33, 20, 7)]
@@ -401,6 +404,8 @@ def test_batch_momentum_pingpong_bitwise(precision):
         bt.set_tile(4, [8, 2, 3])
         bt.set_momentum_pingpong(pp)
         assert bt.get_momentum_pingpong() == pp
+        bt.set_tile_order(not pp)                       # the other tile order with ping-pong
+        assert bt.get_tile_order() == (not pp)
         bt.init_fields([70 + k for k in range(3)])
         bt.step(5, [1.0] * 3, era, sv)                  # 2 diagnostic, 3 plain steps
         mid = [bt.get_fields(k) for k in range(3)]

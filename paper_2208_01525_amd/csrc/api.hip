@@ -993,7 +993,9 @@ int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, do
         c->mpp = false;
         if (rc == MTS_OK) c->err.clear();
     }
-    // and with the other tile order (contiguous runs per XCD or round-robin)
+    // and with the other tile order (contiguous runs per XCD or round-robin),
+    // kept only if at least 1 % faster: at equal speed the XCD runs fetch
+    // less through the fabric
     bool pick_xcd = c->xcd;
     if (rc == MTS_OK) {
         c->mpp = pick_mpp;
@@ -1003,7 +1005,7 @@ int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, do
             (rc = mts_step(c, steps, 1.3, 0.5, 1.0)) == MTS_OK &&
             hip(hipEventRecord(e1, c->stream), "hipEventRecord") &&
             hip(hipEventSynchronize(e1), "hipEventSynchronize") &&
-            hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime") && ms < best) {
+            hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime") && ms < 0.99 * best) {
             best = ms;
             pick_xcd = !pick_xcd;
         }
@@ -1601,7 +1603,7 @@ int mts_batch_autotune(mts_batch *b, int32_t steps, int32_t *ty_out, int32_t *tz
         b->mpp = false;
         if (rc == MTS_OK) b->err.clear();
     }
-    // and with the other tile order (contiguous runs per XCD or round-robin)
+    // and with the other tile order, kept only if at least 1 % faster
     if (rc == MTS_OK) {
         const bool cur = b->xcd;
         b->mpp = pick_mpp;
@@ -1611,7 +1613,7 @@ int mts_batch_autotune(mts_batch *b, int32_t steps, int32_t *ty_out, int32_t *tz
         if ((rc = mts_batch_step(b, 1, eta.data(), era.data(), sv.data(), nullptr, nullptr)) == MTS_OK &&
             (rc = mts_batch_timing_read(b, &ns, &ms)) == MTS_OK &&
             (rc = mts_batch_step(b, steps, eta.data(), era.data(), sv.data(), nullptr, nullptr)) == MTS_OK &&
-            (rc = mts_batch_timing_read(b, &ns, &ms)) == MTS_OK && ms < best)
+            (rc = mts_batch_timing_read(b, &ns, &ms)) == MTS_OK && ms < 0.99 * best)
             best = ms;
         else
             b->xcd = cur;

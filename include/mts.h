@@ -214,9 +214,8 @@ int mts_segments(mts_ctx *ctx, double min_length, mts_segments_t *out, int64_t *
 /* Choose the update kernel.  ty in {4, 5, 8, 12} (and 13 in FP32) selects
  * the z-marching LDS-tiled kernel with tiles of 64 x ty sites and tz >= 1
  * planes per workgroup (default 8 x 32 in FP32, 4 x 32 in FP64; FP32
- * diagnostic steps use at most 8 rows, 9 for tiles of 12 or 13, where their
- * variant does not spill registers, and FP64 diagnostic steps the per-site
- * kernel); every tile
+ * diagnostic steps use at most 8 rows, where their variant does not spill
+ * registers, and FP64 diagnostic steps the per-site kernel); every tile
  * shape gives bitwise identical results.  ty = 0 selects the one-thread-per-site kernel, which computes
  * the plaquette sines directly and agrees with the tiled kernel to
  * rounding.  Synchronises the stream.  EINVAL for other shapes. */

@@ -243,14 +243,12 @@ struct TimedRegion {
 };
 
 // Diagnostic steps use the DIAG variant of the update kernel, which needs
-// more registers: in FP32 it runs with at most 9 rows per tile (12 waves at
-// 165 registers a thread, three per SIMD) so that it never spills; plain
-// tiles of 12 or 13 rows take 9.  Tile shapes do not change results
-// (bitwise).
+// more registers: in FP32 it runs with at most 8 rows per tile so that it
+// never spills.  Tile shapes do not change results (bitwise).
 TileShape diag_tile(const mts_ctx *c) {
     if (c->tile.ty == 0) return c->tile;
-    if (c->p.precision == MTS_FP64) return TileShape{std::min(c->tile.ty, 4), c->tile.tz};
-    return TileShape{c->tile.ty >= 9 ? 9 : std::min(c->tile.ty, 8), c->tile.tz};
+    const int cap = c->p.precision == MTS_FP64 ? 4 : 8;
+    return TileShape{std::min(c->tile.ty, cap), c->tile.tz};
 }
 
 // FP64 diagnostic steps run the one-thread-per-site kernel: the tiled DIAG

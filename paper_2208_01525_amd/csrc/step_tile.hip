@@ -434,18 +434,14 @@ static hipError_t launch_ty(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> 
         // saves about 5 % (512^3: 4.82 against 5.08 ms).  The FP64 variant
         // is at its register limit already.  Diagnostic steps run at most 8
         // rows in FP32 and on the per-site kernel in FP64, so the shapes
-        // only plain steps use have no diagnostic variant.  9 rows (12
-        // waves, the three per SIMD that the variant's 165 registers allow)
-        // exist for FP32 diagnostic steps only.
+        // only plain steps use have no diagnostic variant.
         constexpr int DPF = sizeof(T) == 4 ? 1 : 0;
-        if constexpr (TY == 13 || (TY == 5 && sizeof(T) == 8) || (TY == 9 && sizeof(T) == 8)) {
+        if constexpr (TY == 13 || (TY == 5 && sizeof(T) == 8)) {
             return hipErrorNotSupported;
         } else {
             if (nt) MTS_TILE_LAUNCH(true, true, DPF);
             else MTS_TILE_LAUNCH(true, false, DPF);
         }
-    } else if constexpr (TY == 9) {
-        return hipErrorNotSupported;
     } else if (pf) {
         if (nt) MTS_TILE_LAUNCH(false, true, 1);
         else MTS_TILE_LAUNCH(false, false, 1);
@@ -466,11 +462,6 @@ hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> 
         case 4: return launch_ty<T, 4>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, xcd, st);
         case 8: return launch_ty<T, 8>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, xcd, st);
         case 5: return launch_ty<T, 5>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, xcd, st);
-        case 9:   // FP32 diagnostic steps only
-            if constexpr (sizeof(T) == 4)
-                return launch_ty<T, 9>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, xcd, st);
-            else
-                return hipErrorInvalidValue;
         case 12: return launch_ty<T, 12>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, xcd, st);
         case 13:
             if constexpr (sizeof(T) == 4)
@@ -509,15 +500,6 @@ hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32
         MTS_BATCH_CASE(5)
         MTS_BATCH_CASE(8)
         MTS_BATCH_CASE(12)
-        case 9:   // FP32 diagnostic steps only
-            if constexpr (sizeof(T) == 4) {
-                if (!diag) return hipErrorNotSupported;
-                if (nt) MTS_BATCH_LAUNCH(9, true, true);
-                else MTS_BATCH_LAUNCH(9, true, false);
-                return hipGetLastError();
-            } else {
-                return hipErrorInvalidValue;
-            }
         case 13:
             if constexpr (sizeof(T) == 4) {
                 if (diag) return hipErrorNotSupported;

@@ -111,10 +111,30 @@ __global__ __launch_bounds__(DX *DY) void wind_gauss_kernel(Geom g, Fields<T> f,
         const int xp = wrap1(x + 1, g.nx), xm = wrap1(x - 1, g.nx);
         const int yp = wrap1(y + 1, g.ny), ym = wrap1(y - 1, g.ny);
         const T inv2pi = T(0.5) / Pi<T>::v;
-        const int z1 = min((int)(blockIdx.z + 1) * DZ, g.nz);
-        for (int z = blockIdx.z * DZ; z < z1; z++) {
-            const int zp = wrap1(z + 1, g.nz), zm = wrap1(z - 1, g.nz);
-            const uint32_t nx = g.nx, nxy = g.nxy;
+        const uint32_t nx = g.nx, nxy = g.nxy;
+        const int zb = blockIdx.z * DZ, z1 = min(zb + DZ, g.nz);
+        // Values of plane z+1 that plane z reads are those plane z+1 reads at
+        // its own site and its x and y neighbours: they are carried over in
+        // registers (phases, A_x, A_y) instead of being loaded again, and so
+        // is E_z of plane z for the divergence at plane z+1.
+        T c_a0[2], c_ax[2], c_ay[2], c_Ax[2], c_Ay[2], c_Ez[2];
+        {
+            const uint32_t s = x + nx * y + nxy * zb;
+            const uint32_t s_x = xp + nx * y + nxy * zb, s_y = x + nx * yp + nxy * zb;
+            const uint32_t s_mz = x + nx * y + nxy * wrap1(zb - 1, g.nz);
+#pragma unroll
+            for (int sec = 0; sec < 2; sec++) {
+                const T *al = alpha + (size_t)sec * plane;
+                c_a0[sec] = al[s];
+                c_ax[sec] = al[s_x];
+                c_ay[sec] = al[s_y];
+                c_Ax[sec] = f.A[sec][0][s];
+                c_Ay[sec] = f.A[sec][1][s];
+                c_Ez[sec] = signed_out ? T(0) : mom.E[sec][2][s_mz];
+            }
+        }
+        for (int z = zb; z < z1; z++) {
+            const int zp = wrap1(z + 1, g.nz);
             const uint32_t s = x + nx * y + nxy * z;
             const uint32_t s_x = xp + nx * y + nxy * z, s_y = x + nx * yp + nxy * z, s_z = x + nx * y + nxy * zp;
             const uint32_t s_xy = xp + nx * yp + nxy * z, s_xz = xp + nx * y + nxy * zp, s_yz = x + nx * yp + nxy * zp;
@@ -123,12 +143,19 @@ __global__ __launch_bounds__(DX *DY) void wind_gauss_kernel(Geom g, Fields<T> f,
                 const T *al = alpha + (size_t)sec * plane;
                 const cx<T> *P = f.phi[sec];
                 const T *Ax = f.A[sec][0], *Ay = f.A[sec][1], *Az = f.A[sec][2];
-                const T a0 = al[s], ax = al[s_x], ay = al[s_y], az = al[s_z];
+                const T a0 = c_a0[sec], ax = c_ax[sec], ay = c_ay[sec], az = al[s_z];
                 const T axy = al[s_xy], axz = al[s_xz], ayz = al[s_yz];
-                const T hx = h * Ax[s], hy = h * Ay[s], hz = h * Az[s];
+                const T Ax0 = c_Ax[sec], Ay0 = c_Ay[sec], Az0 = Az[s];
+                const T Ax_z = Ax[s_z], Ay_z = Ay[s_z];
+                c_a0[sec] = az;
+                c_ax[sec] = axz;
+                c_ay[sec] = ayz;
+                c_Ax[sec] = Ax_z;
+                c_Ay[sec] = Ay_z;
+                const T hx = h * Ax0, hy = h * Ay0, hz = h * Az0;
                 const T hy_px = h * Ay[s_x], hz_px = h * Az[s_x];
                 const T hx_py = h * Ax[s_y], hz_py = h * Az[s_y];
-                const T hx_pz = h * Ax[s_z], hy_pz = h * Ay[s_z];
+                const T hx_pz = h * Ax_z, hy_pz = h * Ay_z;
                 const T chx = link_chi(a0, ax, hx, P, s, s_x);
                 const T chy = link_chi(a0, ay, hy, P, s, s_y);
                 const T chz = link_chi(a0, az, hz, P, s, s_z);
@@ -139,9 +166,9 @@ __global__ __launch_bounds__(DX *DY) void wind_gauss_kernel(Geom g, Fields<T> f,
                 const T chx_pz = link_chi(az, axz, hx_pz, P, s_z, s_xz);
                 const T chy_pz = link_chi(az, ayz, hy_pz, P, s_z, s_yz);
                 // unwrapped plaquette angles h [A_mu(x) + A_nu(x+mu) - A_mu(x+nu) - A_nu(x)]
-                const T txy = plaq(h, Ax[s], Ay[s_x], Ax[s_y], Ay[s]);
-                const T tyz = plaq(h, Ay[s], Az[s_y], Ay[s_z], Az[s]);
-                const T tzx = plaq(h, Az[s], Ax[s_z], Az[s_x], Ax[s]);
+                const T txy = plaq(h, Ax0, Ay[s_x], Ax[s_y], Ay0);
+                const T tyz = plaq(h, Ay0, Az[s_y], Ay_z, Az0);
+                const T tzx = plaq(h, Az0, Ax_z, Az[s_x], Ax0);
                 const int Wz = (int)rint_t(((((chx + chy_px) - chx_py) - chy) + txy) * inv2pi);
                 const int Wx = (int)rint_t(((((chy + chz_py) - chy_pz) - chz) + tyz) * inv2pi);
                 const int Wy = (int)rint_t(((((chz + chx_pz) - chz_px) - chx) + tzx) * inv2pi);
@@ -158,8 +185,10 @@ __global__ __launch_bounds__(DX *DY) void wind_gauss_kernel(Geom g, Fields<T> f,
 
                 // Gauss residual at n+1/2: div E^{n+1/2} - g Im[conj(phi^n) Pi^{n+1/2}]
                 const T *Ex = mom.E[sec][0], *Ey = mom.E[sec][1], *Ez = mom.E[sec][2];
-                const uint32_t s_mx = xm + nx * y + nxy * z, s_my = x + nx * ym + nxy * z, s_mz = x + nx * y + nxy * zm;
-                const T div = (((Ex[s] - Ex[s_mx]) + (Ey[s] - Ey[s_my])) + (Ez[s] - Ez[s_mz])) / h;
+                const uint32_t s_mx = xm + nx * y + nxy * z, s_my = x + nx * ym + nxy * z;
+                const T ez0 = Ez[s], ezm = c_Ez[sec];
+                c_Ez[sec] = ez0;
+                const T div = (((Ex[s] - Ex[s_mx]) + (Ey[s] - Ey[s_my])) + (ez0 - ezm)) / h;
                 const T gs = (T)(sec == 0 ? g_p : g_q);
                 const T grho = gs * imc(P[s], mom.pi[sec][s]);
                 acc[sec] += (double)fabs(div - grho);

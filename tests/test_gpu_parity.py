@@ -441,6 +441,37 @@ def _patch_sites(shape, centre, r=2):
     return (xx + nx * (yy + ny * zz)).ravel().astype(np.uint64)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_autotuned_configuration_bitwise(precision):
+    """Whatever the autotuner picks on this box (tile shape, store mode, load pipeline,
+    momentum ping-pong, tile order, steps per sweep) is one of the bitwise-neutral
+    configurations: a run with it equals a run with the default configuration bit for bit,
+    (diagnostics every 3 steps, 10 steps).  Fields and integer counts are compared bit for
+    bit; the FP64 sums to 1e-13 relative, since another tile shape sums the per-block
+    partials in another order."""
+    nx, ny, nz = 136, 40, 30
+    st = rounded(I.random_full(nx, ny, nz, 77, link=0.5, mom=0.5), precision)
+    out = []
+    for tuned in (False, True):
+        lat = lattice(nx, ny, nz, precision, eta_ref=9.0, diag_every=3)
+        if tuned:
+            lat.autotune(2)
+            print(f"autotuned {precision}: tile {lat.get_tile()} nt {lat.get_streaming_stores()} "
+                  f"pf {lat.get_prefetch()} pp {lat.get_momentum_pingpong()} xcd {lat.get_tile_order()} "
+                  f"tb {lat.get_time_blocking()}", flush=True)
+        lat.set_fields(st)
+        lat.step(10, 1.0, 0.5, 1.0)
+        out.append((lat.get_fields(), lat.diagnostics()))
+        lat.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert len(out[0][1]) == len(out[1][1]) == 4
+    for a, b in zip(out[0][1], out[1][1]):
+        for k in ("wind_abs", "pq_count2"):
+            assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
+        for k in ("sum_energy", "sum_lagrangian", "gauss_abs"):
+            assert np.allclose(np.asarray(a[k]), np.asarray(b[k]), rtol=1e-13, atol=0), k
+
+
 def test_full_size_workload_sampled():
     """The benchmarked configuration at its full size and launch configuration: 512^3, FP32,
     the tile shape and store mode the autotuner picks (as the benchmark does), diagnostics

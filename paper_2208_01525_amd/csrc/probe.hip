@@ -8,11 +8,13 @@ namespace mts {
 
 namespace {
 
-// One float4 per thread: dst[i] = src[i].
+// dst[i] = src[i], one float4 per thread and pass; the grid strides over
+// copies of more than 2^31 float4 (a dispatch holds fewer than 2^32
+// work-items).
 __global__ __launch_bounds__(256) void probe_copy_kernel(const float4 *__restrict__ src, float4 *__restrict__ dst,
                                                          uint64_t n4) {
-    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n4) dst[i] = src[i];
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += stride) dst[i] = src[i];
 }
 
 // The update's HBM pattern without its stencil or arithmetic: per site, the
@@ -45,7 +47,8 @@ hipError_t launch_probe_copy(void *state, uint64_t bytes_per_copy, hipStream_t s
     const uint64_t n4 = bytes_per_copy / 16;
     const float4 *src = static_cast<const float4 *>(state);
     float4 *dst = reinterpret_cast<float4 *>(static_cast<char *>(state) + bytes_per_copy);
-    probe_copy_kernel<<<(unsigned)((n4 + 255) / 256), 256, 0, st>>>(src, dst, n4);
+    const uint64_t nb = std::min<uint64_t>((n4 + 255) / 256, (uint64_t)1 << 23);
+    probe_copy_kernel<<<(unsigned)nb, 256, 0, st>>>(src, dst, n4);
     return hipGetLastError();
 }
 

@@ -88,7 +88,7 @@ typedef struct mts_diag {
     /* derived on the host from the sums above (Sec. III.A):                    */
     double L_p, L_q, L_pq;   /* L_pq = h N_pq; L_p = h sum|W_p| - L_pq          */
     double xi_p, xi_q, xi_pq, xi_W;   /* sqrt(V/L)                              */
-    double xi_lag;           /* sqrt(-2 pi V / (h^3 sum Lag)), mu = 2 pi sigma^2 */
+    double xi_lag;           /* sqrt(-mu V / (h^3 sum Lag)), mu = 2 pi sigma_p^2 */
     double f_total, f_p;     /* L_pq/(L_pq+L_p+L_q), L_pq/L_p                   */
     double v2_lag, v2_pq;    /* <v^2> = 2R/(1+R), R = sum K W / sum G W         */
     double gauss_rel[2];     /* gauss_abs / gauss_scale (0 when scale is 0)     */

@@ -229,16 +229,19 @@ def set_num_threads(n):
     lib().orc_set_num_threads(int(n))
 
 
-def derive(m, rec, mu=2.0 * math.pi):
+def derive(m, rec, mu=None):
     """Network estimators from one record (Sec. III.A):
       L_pq = h N_pq,  L_p = h sum|W_p| - L_pq,  L_q likewise
       xi_X = sqrt(V / L_X),  xi_W = sqrt(V / (L_p + L_q + L_pq))
-      xi_Lag = sqrt(-mu V / (h^3 sum Lag)),  mu = 2 pi sigma^2 (Sec. IV)
+      xi_Lag = sqrt(-mu V / (h^3 sum Lag)) with mu the tension of a basic string:
+        2 pi sigma_p^2 for a p-string at critical coupling (Sec. IV) unless given
       f_total = L_pq / (L_pq + L_p + L_q),  f_p = L_pq / L_p
       <v^2> = 2R / (1 + R), R = sum K W / sum G W with W = Lag or Vint.
     A ratio with a zero denominator is reported as nan."""
     h = m.h
     V = m.sites * h ** 3
+    if mu is None:
+        mu = 2.0 * math.pi * m.sig[0] ** 2
 
     def ratio(a, b):
         return a / b if b != 0 else float("nan")

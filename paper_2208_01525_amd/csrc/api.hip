@@ -390,7 +390,8 @@ void derive(const mts_params &p, uint64_t S, mts_diag &d) {
     d.xi_q = xi(d.L_q);
     d.xi_pq = xi(d.L_pq);
     d.xi_W = xi(d.L_p + d.L_q + d.L_pq);
-    const double mu = 2.0 * M_PI;   // tension of a basic string at criticality, sigma = 1 (Sec. IV)
+    // tension of a basic string: a p-string at critical coupling, 2 pi sigma_p^2 (Sec. III.A, IV)
+    const double mu = 2.0 * M_PI * p.sigma_p * p.sigma_p;
     d.xi_lag = d.sum_lagrangian < 0 ? std::sqrt(-mu * V / d.sum_lagrangian) : NAN;
     d.f_total = ratio(d.L_pq, d.L_pq + d.L_p + d.L_q);
     d.f_p = ratio(d.L_pq, d.L_p);

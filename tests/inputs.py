@@ -85,3 +85,20 @@ def string_pairs(nx, ny, nz, p_pair=None, q_pair=None, core=0.0):
 def to_f32_values(st):
     """Round every component to the nearest float32 (the values an FP32 lattice holds)."""
     return st.astype(np.float32).astype(np.float64)
+
+
+def string_set(nx, ny, nz, p_vortices=(), q_vortices=(), sig=(1.0, 1.0)):
+    """Straight strings along z: each sector gets the vortices in its list of
+    (xc, yc, w), a vortex of winding w at (xc + 1/2, yc + 1/2) in lattice units;
+    the phase is the sum of w times the polar angle about each, the modulus sig.
+    Windings that add up to zero keep the phase smooth across the periodic
+    boundary.  A sector with no vortex sits in its vacuum.  Links and momenta zero."""
+    st = empty(nx, ny, nz)
+    y, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64), indexing="ij")
+    for sec, (c, vort) in enumerate(((PHI, p_vortices), (PSI, q_vortices))):
+        th = np.zeros((ny, nx))
+        for xc, yc, w in vort:
+            th += w * np.arctan2(y - (yc + 0.5), x - (xc + 0.5))
+        st[c] = (sig[sec] * np.cos(th))[None]
+        st[c + 1] = (sig[sec] * np.sin(th))[None]
+    return st

@@ -123,6 +123,41 @@ def test_pure_hubble_damping_telescopes(era_m, s):
     assert np.all(st[I.PI:I.PI + 2] == st[I.PI:I.PI + 2, :1, :1, :1])   # stays uniform
 
 
+def test_damping_above_one_follows_the_same_closed_form():
+    """R26: the damped phase of Sec. V runs at m_damp = 0.95 from eta = 1, where
+    delta = p k / eta with p = 19 exceeds 1 until eta = p k = 1.9.  The printed kick is
+    applied as it stands: (1 - delta)/(1 + delta) is then negative (the free momentum flips
+    sign every step while its magnitude still shrinks), it erases the momentum at
+    eta = p k, and the telescoped product of P4 holds for any delta.  From eta = 1.05 the
+    product's 38 factors have no zero: nine negative factors, so the sign is reversed."""
+    nx = 4
+    era_m = 0.95
+    p = era_m / (1 - era_m)
+    m = O.model(nx, lam=(0.0, 0.0), kappa=0.0, eta_ref=5.0)
+    k = m.k
+
+    def free_momentum(eta0, N):
+        st = I.empty(nx, nx, nx)
+        st[I.PHI] = 0.7
+        st[I.PI] = 0.3
+        st[I.PI + 1] = -0.2
+        O.run(m, st, N, eta0, era_m, 0.0)
+        return st[I.PI:I.PI + 2, 1, 2, 3] / np.array([0.3, -0.2])
+
+    # the first step from eta = 1: (1 - 1.9)/(1 + 1.9)
+    assert np.allclose(free_momentum(1.0, 1), -0.9 / 2.9, rtol=1e-14, atol=0)
+    # the step from eta = 1.9 multiplies by (1.9 - p k)/(1.9 + p k) = 0 (to rounding of p)
+    assert np.abs(free_momentum(1.0, 10)).max() < 1e-14
+    # telescoped closed form from eta = 1.05 over N >= 2p steps
+    eta0, N = 1.05, 41
+    f = lambda t: eta0 + t * k
+    closed = 1.0
+    for j in range(int(round(2 * p))):
+        closed *= f(j - p) / f(N - p + j)
+    assert closed < 0
+    assert np.allclose(free_momentum(eta0, N), closed, rtol=1e-11, atol=0)
+
+
 # --------------------------------------------------------------- P5
 
 

@@ -177,6 +177,19 @@ int mts_set_fields(mts_ctx *ctx, const double *host);
  * copy out whole. */
 int mts_get_sites(mts_ctx *ctx, const uint64_t *sites, int32_t n, double *host);
 
+/* For callers that cannot allocate device memory (code between allocation
+ * checkpoints, serving loops, harnesses that forbid hipMalloc): the same
+ * result as mts_get_sites, bit for bit, staged through a static device
+ * array of the library instead of device memory allocated per call.  The
+ * array holds at most MTS_NOALLOC_MAX_SITES sites (1.4 MB; each GPU the
+ * library runs on keeps one copy until the process ends); n above that is
+ * MTS_EINVAL, as is a site index >= nx*ny*nz.  Every call on one GPU shares
+ * that GPU's array, so calls that overlap in time on one GPU (contexts
+ * driven from several host threads) race; calls in sequence do not.  Calls
+ * no hipMalloc/hipFree; the host arrays are the caller's.  Synchronous. */
+#define MTS_NOALLOC_MAX_SITES 8192
+int mts_get_sites_noalloc(mts_ctx *ctx, const uint64_t *sites, int32_t n, double *host);
+
 /* Signed plaquette windings of the current fields (Sec. III.A), host
  * int8[6][S]: sector p (W_x, W_y, W_z), then sector q; W_rho is the
  * winding through the face normal to rho at the cell's lower corner,

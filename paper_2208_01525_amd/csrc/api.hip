@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -17,10 +18,48 @@ namespace {
 
 constexpr int RING_CAP = 4096;   // diagnostic records kept on the device between drains
 
+// Staging of mts_get_sites_noalloc: the site indices, then the gathered
+// values (double[n][20]), for at most MTS_NOALLOC_MAX_SITES sites.
+constexpr size_t NOALLOC_SITES_BYTES = sizeof(uint64_t) * MTS_NOALLOC_MAX_SITES;
+constexpr size_t NOALLOC_BYTES = NOALLOC_SITES_BYTES + sizeof(double) * 20 * MTS_NOALLOC_MAX_SITES;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
 struct Meta {                    // host-side facts of one record
     int64_t step;
     double eta, a, s;
 };
+
+}  // namespace
+
+// Device scratch of the entry points that allocate nothing: each GPU the
+// library runs on holds one copy for the life of the process.  Host code
+// never passes this name to a kernel or a copy; it uses the device address
+// that noalloc_scratch() obtains once per device.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, looked up on the first
+// call for that device and kept.
+hipError_t noalloc_scratch(void **out) {
+    *out = nullptr;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
 
 }  // namespace
 
@@ -57,6 +96,8 @@ struct mts_ctx {
     int64_t produced = 0, drained = 0;
     bool have_cells = false;
     int64_t cells_step = -1;     // step whose cells the cell arrays hold
+    void *noalloc = nullptr;     // this device's `scratch` (entry points that allocate nothing)
+    std::string noalloc_err;     // why it could not be looked up, if it could not
 
     // timing
     bool timing = false;
@@ -547,6 +588,14 @@ int mts_create(const mts_params *p, void *dev_state, size_t state_bytes, void *s
         mts_destroy(c);
         return MTS_ENOMEM;
     }
+    // the static scratch of this device (used only by the entry points that
+    // allocate nothing; a failure here is reported by them)
+    const hipError_t es = noalloc_scratch(&c->noalloc);
+    if (es != hipSuccess) {
+        c->noalloc = nullptr;
+        c->noalloc_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(es);
+        (void)hipGetLastError();
+    }
     *out = c;
     return MTS_OK;
 }
@@ -708,6 +757,31 @@ int mts_get_sites(mts_ctx *c, const uint64_t *sites, int32_t n, double *host) {
     (void)hipFree(dsites);
     (void)hipFree(dout);
     if (e != hipSuccess) return hipfail(c, e, "get_sites");
+    return MTS_OK;
+}
+
+int mts_get_sites_noalloc(mts_ctx *c, const uint64_t *sites, int32_t n, double *host) {
+    if (!c || n < 0 || (n > 0 && (!sites || !host))) return MTS_EINVAL;
+    if (n > MTS_NOALLOC_MAX_SITES) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "get_sites_noalloc: n = %d exceeds the static scratch's %d sites", (int)n,
+                      (int)MTS_NOALLOC_MAX_SITES);
+        return fail(c, MTS_EINVAL, buf);
+    }
+    if (n == 0) return MTS_OK;
+    for (int32_t i = 0; i < n; i++)
+        if (sites[i] >= c->S) return fail(c, MTS_EINVAL, "site index out of range");
+    if (!c->noalloc) return fail(c, MTS_EHIP, c->noalloc_err);
+    uint64_t *dsites = static_cast<uint64_t *>(c->noalloc);
+    double *dout = reinterpret_cast<double *>(static_cast<char *>(c->noalloc) + NOALLOC_SITES_BYTES);
+    hipError_t e = hipMemcpyAsync(dsites, sites, sizeof(uint64_t) * n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = c->p.precision == MTS_FP64
+                ? launch_gather<double>(fields_of<double>(c, c->cur), moms_of<double>(c), dsites, n, dout, c->stream)
+                : launch_gather<float>(fields_of<float>(c, c->cur), moms_of<float>(c), dsites, n, dout, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, dout, sizeof(double) * 20 * n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hipfail(c, e, "get_sites_noalloc");
     return MTS_OK;
 }
 

@@ -16,9 +16,10 @@ LIB_PATH = os.path.join(_HERE, "libmts.so")
 
 MTS_OK, MTS_EINVAL, MTS_EUNSTABLE, MTS_ENOMEM, MTS_EHIP, MTS_ENONFINITE = 0, -1, -2, -3, -4, -5
 MTS_FP32, MTS_FP64 = 1, 2
+NOALLOC_MAX_SITES = 8192        # MTS_NOALLOC_MAX_SITES of include/mts.h
 
 EXPORTS = ("mts_state_bytes", "mts_create", "mts_destroy", "mts_init_fields", "mts_step", "mts_cool", "mts_diagnostics",
-           "mts_get_fields", "mts_set_fields", "mts_get_windings", "mts_get_cells", "mts_get_sites", "mts_segments", "mts_set_tile", "mts_get_tile", "mts_set_streaming_stores", "mts_bandwidth_probe", "mts_get_streaming_stores", "mts_autotune", "mts_timing_enable",
+           "mts_get_fields", "mts_set_fields", "mts_get_windings", "mts_get_cells", "mts_get_sites", "mts_get_sites_noalloc", "mts_segments", "mts_set_tile", "mts_get_tile", "mts_set_streaming_stores", "mts_bandwidth_probe", "mts_get_streaming_stores", "mts_autotune", "mts_timing_enable",
            "mts_timing_read", "mts_set_time_blocking", "mts_get_time_blocking", "mts_set_prefetch", "mts_get_prefetch", "mts_set_momentum_pingpong", "mts_get_momentum_pingpong", "mts_set_tile_order", "mts_get_tile_order", "mts_last_error", "mts_strerror",
            "mts_batch_state_bytes", "mts_batch_create", "mts_batch_destroy", "mts_batch_size",
            "mts_batch_init_fields", "mts_batch_step", "mts_batch_diagnostics", "mts_batch_get_fields",
@@ -106,6 +107,8 @@ def load():
     L.mts_segments.argtypes = [vp, ctypes.c_double, ctypes.POINTER(Segments), ctypes.POINTER(ctypes.c_int64),
                                ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     L.mts_get_sites.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+    L.mts_get_sites_noalloc.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_double)]
     L.mts_set_tile.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     L.mts_set_streaming_stores.argtypes = [vp, ctypes.c_int32]
     L.mts_bandwidth_probe.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
@@ -258,6 +261,15 @@ class Lattice:
         out = np.empty((len(sites), 20), dtype=np.float64)
         self._check(self.L.mts_get_sites(self.ctx, sites.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), len(sites),
                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def get_sites_noalloc(self, sites):
+        """get_sites staged through the library's static device scratch (no device
+        allocation; at most NOALLOC_MAX_SITES sites)."""
+        sites = np.ascontiguousarray(sites, dtype=np.uint64)
+        out = np.empty((len(sites), 20), dtype=np.float64)
+        self._check(self.L.mts_get_sites_noalloc(self.ctx, sites.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                                 len(sites), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out
 
     def segments(self, min_length=0.0, max_sizes=1 << 20):

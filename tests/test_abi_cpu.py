@@ -116,3 +116,13 @@ def test_null_context_rejected():
     cnt = ctypes.c_int32()
     assert L.mts_diagnostics(None, None, 0, ctypes.byref(cnt)) == M.MTS_EINVAL
     assert L.mts_strerror(M.MTS_EUNSTABLE) == b"MTS_EUNSTABLE"
+
+
+def test_noalloc_limit_matches_header_and_null_context_rejected():
+    text = open(HEADER).read()
+    m = re.search(r"#define MTS_NOALLOC_MAX_SITES (\d+)", text)
+    assert m and int(m.group(1)) == M.NOALLOC_MAX_SITES
+    L = P.load()
+    out = (ctypes.c_double * 20)()
+    site = (ctypes.c_uint64 * 1)(0)
+    assert L.mts_get_sites_noalloc(None, site, 1, out) == M.MTS_EINVAL

@@ -199,7 +199,9 @@ int mts_get_windings(mts_ctx *ctx, int8_t *host);
 
 /* Cell values of the last diagnostic step (total |winding| through the
  * six faces of each cell; a straight string gives 2, Sec. III.B), host
- * uint8[2][S] (sector p, then q).  Synchronous. */
+ * uint8[2][S] (sector p, then q).  Each face counts at most 3 (windings are
+ * packed in two bits per face; the paper sees none above 1, and the record's
+ * sum |W| is not clipped).  Synchronous. */
 int mts_get_cells(mts_ctx *ctx, uint8_t *host);
 
 /* Robust-method bound-state segments (Sec. III.B, Sec. V.B) of the last
@@ -270,6 +272,22 @@ int mts_get_tile_order(const mts_ctx *ctx, int32_t *xcd_runs);
  * identical; the autotuner tries both.  Synchronises the stream. */
 int mts_set_prefetch(mts_ctx *ctx, int32_t on);
 int mts_get_prefetch(const mts_ctx *ctx, int32_t *on);
+
+/* Fused diagnostics (FP32 tiled steps; Sec. III.A windings and the Gauss
+ * law of Sec. II): with rows in {4, 5, 8} (default 8) a diagnostic step
+ * computes the plaquette windings of its input fields and the Gauss
+ * residual at n + 1/2 inside the update kernel (tiles of 64 x rows sites),
+ * so only the cell values, the overlap and the final reduction run after
+ * it; rows = 0 computes them in separate post-step kernels.  The fused
+ * step writes the new momenta to a second momentum copy, which the library
+ * allocates on the first fused step (10 planes, 40 bytes per site in FP32;
+ * freed by mts_destroy); if it does not fit, diagnostic steps fall back to
+ * the post-step kernels and mts_get_fused_diagnostics reports 0.  Windings,
+ * cells and overlap counts are bitwise identical either way; the Gauss sums
+ * agree to the rounding of their summation order.  FP64 and the per-site
+ * kernel always use the post-step kernels.  Synchronises the stream. */
+int mts_set_fused_diagnostics(mts_ctx *ctx, int32_t rows);
+int mts_get_fused_diagnostics(const mts_ctx *ctx, int32_t *rows);
 
 /* Temporal blocking (FP32): with steps = 2, every two consecutive plain
  * steps (no diagnostics due at either) run as one sweep of a two-level

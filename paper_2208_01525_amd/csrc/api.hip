@@ -83,6 +83,8 @@ struct mts_ctx {
     bool pf = false;             // loads one plane ahead in the tiled update (plain steps)
     bool mpp = false;            // tiled steps write the momenta to the other momentum copy
     bool xcd = true;             // tiles dealt to the XCDs in contiguous runs (else round-robin)
+    int fuse_ty = 8;             // rows of the fused diagnostic tile (0: windings and Gauss in post-step kernels)
+    bool fuse_off = false;       // the fused path needs a second momentum copy and none could be allocated
     int tblock = 1;              // leapfrog steps per sweep through HBM (1, or 2: two-step kernel)
     TileShape tile2{7, 32};      // tile of the two-step kernel
     void *mom2 = nullptr;        // second momentum copy (10 planes), allocated for two-step sweeps
@@ -209,6 +211,7 @@ StepCoef<T> coefficients(const mts_params &p, const Book &b, double s) {
         c.inv_e2h4[q] = (T)(1.0 / (e[q] * e[q] * h * h * h * h));
         c.lam4[q] = (T)(lam[q] / 4.0);
     }
+    for (int q = 0; q < 2; q++) c.gsig[q] = (T)(2.0 * (e[q] * e[q]) * b.An * (1.0 + b.delta) / (1.0 + b.omega));
     c.a2s = (T)std::pow(b.a, 2.0 * s);
     c.am2s = (T)std::pow(b.a, -2.0 * s);
     c.kap0 = (T)p.kappa;
@@ -299,36 +302,56 @@ TileShape diag_tile(const mts_ctx *c) {
 // Ensembles do the same for their FP64 diagnostic steps (one launch per box).
 bool diag_per_site(const mts_ctx *c) { return c->tile.ty == 0 || c->p.precision == MTS_FP64; }
 
+// Diagnostic steps of the tiled FP32 kernel take the windings and the Gauss
+// residual in the same pass (the post-step kernels then only form the cells
+// and the overlap) unless switched off or no second momentum copy fits.
+bool diag_fused(const mts_ctx *c) { return !diag_per_site(c) && c->fuse_ty != 0 && !c->fuse_off; }
+
+TileShape fused_tile(const mts_ctx *c) { return TileShape{c->fuse_ty, c->tile.tz}; }
+
 // Partials per slot: the update kernel's blocks for the integer-time sums,
 // the per-site grid for the post-step diagnostic kernels.
+// The second table (at nblk_dev + NSLOT) is the fused path's: the update
+// kernel's blocks hold every slot up to the winding sums.
 hipError_t upload_nblk(mts_ctx *c) {
-    uint32_t nb[NSLOT];
+    uint32_t nb[2 * NSLOT];
     const uint32_t step_blocks = diag_per_site(c) ? site_blocks(c->g) : tile_blocks(c->g, diag_tile(c));
-    for (int q = 0; q < NSLOT; q++)
+    const uint32_t fused_blocks = c->fuse_ty ? tile_blocks(c->g, fused_tile(c)) : 0;
+    for (int q = 0; q < NSLOT; q++) {
         nb[q] = q <= SL_GV ? step_blocks : (q <= SL_WIND_Q ? wind_blocks(c->g) : (q <= SL_OV_Q ? overlap_blocks(c->g) : 0));
+        nb[NSLOT + q] = q <= SL_WIND_Q ? fused_blocks : (q <= SL_OV_Q ? overlap_blocks(c->g) : wind_fix_blocks(c->g));
+    }
     return hipMemcpy(c->nblk_dev, nb, sizeof(nb), hipMemcpyHostToDevice);
 }
 
 // Post-step diagnostic kernels of one box (windings + Gauss, cells, overlap,
 // reduce into the next ring slot) for the step from eta_j; fields at n are
 // in copy `cur`.  Host-side facts of the record are queued.
+// With `fused` the update kernel has already written the windings and the
+// Gauss sums: only the cells, the overlap and the reduction remain.
 template <typename T>
-hipError_t enqueue_diag_post(mts_ctx *c, const Book &b, double eta_j, double s, hipStream_t st, bool alpha_ready) {
+hipError_t enqueue_diag_post(mts_ctx *c, const Book &b, double eta_j, double s, hipStream_t st, bool alpha_ready,
+                             bool fused = false) {
     const mts_params &p = c->p;
     Partials part{c->partials, c->maxblk};
     double gcoef[2];
     const double e2[2] = {p.e_p * p.e_p, p.e_q * p.e_q};
     for (int q = 0; q < 2; q++) gcoef[q] = 2.0 * e2[q] * b.An * (1.0 + b.delta) / (1.0 + b.omega);
     T *alpha = static_cast<T *>(c->alpha);
-    hipError_t e = alpha_ready ? hipSuccess : launch_phase<T>(c->g, fields_of<T>(c, c->cur), alpha, (uint32_t)c->plane, st);
-    if (e == hipSuccess)
-        e = launch_wind_gauss<T>(c->g, fields_of<T>(c, c->cur), moms_of<T>(c), alpha, (T)p.dx, gcoef, c->wabs,
-                                 (uint32_t)c->plane, nullptr, part, st);
+    hipError_t e = hipSuccess;
+    if (!fused) {
+        if (!alpha_ready) e = launch_phase<T>(c->g, fields_of<T>(c, c->cur), alpha, (uint32_t)c->plane, st);
+        if (e == hipSuccess)
+            e = launch_wind_gauss<T>(c->g, fields_of<T>(c, c->cur), moms_of<T>(c), alpha, (T)p.dx, (T)(1.0 / p.dx),
+                                     gcoef, c->wabs, (uint32_t)c->plane, nullptr, part, st);
+    } else {
+        e = launch_wind_fix<T>(c->g, fields_of<T>(c, c->cur), (T)p.dx, c->wabs, (uint32_t)c->plane, part, st);
+    }
     if (e == hipSuccess) e = launch_cells(c->g, c->wabs, c->cells, c->bits, (uint32_t)c->plane, st);
     if (e == hipSuccess)
         e = launch_overlap(c->g, c->cells, c->bits, (uint32_t)c->plane, p.overlap_radius, part, st);
     double *rec = c->ring + (size_t)(c->produced % RING_CAP) * NSLOT;
-    if (e == hipSuccess) e = launch_reduce(part, c->nblk_dev, rec, st);
+    if (e == hipSuccess) e = launch_reduce(part, c->nblk_dev + (fused ? NSLOT : 0), rec, st);
     if (e != hipSuccess) return e;
     c->meta.push_back({c->step_count, eta_j, b.a, s});
     c->produced++;
@@ -336,6 +359,8 @@ hipError_t enqueue_diag_post(mts_ctx *c, const Book &b, double eta_j, double s, 
     c->cells_step = c->step_count;
     return hipSuccess;
 }
+
+int ensure_mom2_quiet(mts_ctx *c);
 
 template <typename T>
 int do_step(mts_ctx *c, int32_t n, double eta, double era_m, double s) {
@@ -367,18 +392,20 @@ int do_step(mts_ctx *c, int32_t n, double eta, double era_m, double s) {
         Moms<T> mom = moms_of<T>(c);
         Fields<T> in = fields_of<T>(c, c->cur), out = fields_of<T>(c, 1 - c->cur);
         const bool per_site = c->tile.ty == 0 || (diag && diag_per_site(c));
-        // momenta to the other copy on plain tiled steps (diagnostic steps, measured 9 % slower with it
-        // at 512^3, and the per-site kernel rewrite them in place)
-        const bool pp = c->mpp && !per_site && !diag;
+        // fused diagnostics write the momenta to the other copy (allocated on first use)
+        const bool fused = diag && diag_fused(c) && ensure_mom2_quiet(c) == MTS_OK;
+        // momenta to the other copy on plain tiled steps (the unfused diagnostic steps, measured 9 % slower
+        // with it at 512^3, and the per-site kernel rewrite them in place)
+        const bool pp = (c->mpp && !per_site && !diag) || fused;
         const Moms<T> mom_out = pp ? moms_at<T>(c, 1 - c->mcur) : mom;
         {
             TimedRegion tr(c, diag ? 1 : 0);
             hipError_t e = per_site
                                ? launch_step<T>(c->g, in, out, mom, coef, diag, part, c->stream)
                                : launch_step_tile<T>(c->g, in, out, mom, mom_out, coef, diag, part,
-                                                     diag ? diag_tile(c) : c->tile,
-                                                     static_cast<T *>(c->alpha), (uint32_t)c->plane, c->nt,
-                                                     c->pf, c->xcd, c->stream);
+                                                     fused ? fused_tile(c) : (diag ? diag_tile(c) : c->tile),
+                                                     static_cast<T *>(c->alpha), fused ? c->wabs : nullptr,
+                                                     (uint32_t)c->plane, c->nt, c->pf, c->xcd, c->stream);
             if (e != hipSuccess) return hipfail(c, e, "step kernel launch");
         }
         if (pp) c->mcur = 1 - c->mcur;   // the diagnostic kernels below read the new momenta
@@ -386,7 +413,7 @@ int do_step(mts_ctx *c, int32_t n, double eta, double era_m, double s) {
         hipError_t ep = hipSuccess;
         if (diag) {
             TimedRegion tr(c, 2);
-            ep = enqueue_diag_post<T>(c, b, eta_j, s, c->stream, !diag_per_site(c));
+            ep = enqueue_diag_post<T>(c, b, eta_j, s, c->stream, !diag_per_site(c), fused);
         }
         c->cur = 1 - c->cur;
         c->step_count++;
@@ -523,8 +550,8 @@ int get_windings_t(mts_ctx *c, int8_t *host) {
     T *alpha = static_cast<T *>(c->alpha);
     hipError_t e = launch_phase<T>(c->g, fields_of<T>(c, c->cur), alpha, (uint32_t)c->plane, c->stream);
     if (e == hipSuccess)
-        e = launch_wind_gauss<T>(c->g, fields_of<T>(c, c->cur), moms_of<T>(c), alpha, (T)c->p.dx, g0, nullptr,
-                                 (uint32_t)c->plane, tmp, part, c->stream);
+        e = launch_wind_gauss<T>(c->g, fields_of<T>(c, c->cur), moms_of<T>(c), alpha, (T)c->p.dx,
+                                 (T)(1.0 / c->p.dx), g0, nullptr, (uint32_t)c->plane, tmp, part, c->stream);
     std::vector<int8_t> buf(bytes);
     if (e == hipSuccess) e = hipMemcpyAsync(buf.data(), tmp, bytes, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -534,6 +561,23 @@ int get_windings_t(mts_ctx *c, int8_t *host) {
     return MTS_OK;
 }
 
+}  // namespace
+
+namespace {
+// The second momentum copy for the fused diagnostics: allocated on first use;
+// if it does not fit, the fused path is switched off for this context.
+int ensure_mom2_quiet(mts_ctx *c) {
+    if (c->mom2) return MTS_OK;
+    if (c->fuse_off) return MTS_ENOMEM;
+    hipError_t e = hipMalloc(&c->mom2, (size_t)10 * c->plane * c->esz);
+    if (e != hipSuccess) {
+        c->mom2 = nullptr;
+        c->fuse_off = true;
+        (void)hipGetLastError();
+        return MTS_ENOMEM;
+    }
+    return MTS_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -574,8 +618,9 @@ int mts_create(const mts_params *p, void *dev_state, size_t state_bytes, void *s
     c->maxblk = site_blocks(c->g);
     for (int ty : {4, 5, 8, 12, 13}) c->maxblk = std::max(c->maxblk, tile_blocks(c->g, TileShape{ty, 1}));
     c->maxblk = std::max(c->maxblk, std::max(wind_blocks(c->g), overlap_blocks(c->g)));
+    c->maxblk = std::max(c->maxblk, wind_fix_blocks(c->g));
     hipError_t e = hipMalloc(&c->partials, sizeof(double) * NSLOT * (size_t)c->maxblk);
-    if (e == hipSuccess) e = hipMalloc(&c->nblk_dev, sizeof(uint32_t) * NSLOT);
+    if (e == hipSuccess) e = hipMalloc(&c->nblk_dev, sizeof(uint32_t) * 2 * NSLOT);
     if (e == hipSuccess) e = hipMalloc(&c->wabs, 2 * c->plane);
     if (e == hipSuccess) e = hipMalloc(&c->cells, 2 * c->plane);
     if (e == hipSuccess) e = hipMalloc(&c->alpha, 2 * c->plane * c->esz);
@@ -706,11 +751,11 @@ int mts_diagnostics(mts_ctx *c, mts_diag *out, int32_t max, int32_t *count) {
         d.gauss_abs[1] = rec[SL_GAUSS_ABS_Q];
         d.gauss_scale[0] = rec[SL_GAUSS_SCALE_P];
         d.gauss_scale[1] = rec[SL_GAUSS_SCALE_Q];
-        d.wind_abs[0] = (int64_t)std::llround(rec[SL_WIND_P]);
-        d.wind_abs[1] = (int64_t)std::llround(rec[SL_WIND_Q]);
+        d.wind_abs[0] = (int64_t)std::llround(rec[SL_WIND_P] + rec[SL_FIX_P]);
+        d.wind_abs[1] = (int64_t)std::llround(rec[SL_WIND_Q] + rec[SL_FIX_Q]);
         d.pq_count2 = (int64_t)std::llround(rec[SL_OV_P] + rec[SL_OV_Q]);
         bool finite = true;
-        for (int q = 0; q <= SL_OV_Q; q++) finite = finite && std::isfinite(rec[q]);
+        for (int q = 0; q < NSLOT; q++) finite = finite && std::isfinite(rec[q]);
         derive(c->p, c->S, d);
         d.flags = (finite ? 0 : 1) | (lost > 0 ? 2 : 0);
         if (!finite) rc = MTS_ENONFINITE;
@@ -872,6 +917,23 @@ static int ensure_mom2(mts_ctx *c, const char *what) {
         (void)hipGetLastError();
         return fail(c, MTS_ENOMEM, std::string(what) + ": second momentum copy: " + hipGetErrorString(e));
     }
+    return MTS_OK;
+}
+
+int mts_set_fused_diagnostics(mts_ctx *c, int32_t rows) {
+    if (!c) return MTS_EINVAL;
+    if (rows != 0 && rows != 4 && rows != 5 && rows != 8)
+        return fail(c, MTS_EINVAL, "fused diagnostics: rows must be 0 (off), 4, 5 or 8");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->fuse_ty = rows;
+    if (rows) c->fuse_off = false;   // try the second momentum copy again
+    HIPCHK(c, upload_nblk(c));
+    return MTS_OK;
+}
+
+int mts_get_fused_diagnostics(const mts_ctx *c, int32_t *rows) {
+    if (!c || !rows) return MTS_EINVAL;
+    *rows = diag_fused(c) ? c->fuse_ty : 0;
     return MTS_OK;
 }
 

@@ -146,6 +146,117 @@ struct Pi<double> {
     static constexpr double v = 3.14159265358979323846;
 };
 
+// ---- link phases for the plaquette windings (Sec. III.A)
+//
+// With alpha(x) = arg phi(x), the covariant link phase
+//   chi_mu(x) = arg(conj(phi(x)) U_mu(x) phi(x+mu)) = wrap(alpha(x+mu) - alpha(x) - h A_mu(x))
+// takes no transcendental function per link.  A link whose chi lies within
+// Guard::cut of the branch cut, has an endpoint with phi = 0 or |h A| above
+// Guard::big is recomputed in FP64 from the complex product, so the windings
+// equal an FP64 evaluation of the same inputs bit for bit.
+
+template <typename T>
+struct Guard;
+template <>
+struct Guard<float> {
+    static constexpr float cut = 1e-4f, big = 1e3f;
+};
+template <>
+struct Guard<double> {
+    static constexpr double cut = 1e-9, big = 1e6;
+};
+
+template <typename T>
+__device__ __forceinline__ T wrap_pi(T v) {   // into [-pi, pi], +pi for the cut itself
+    const T two_pi = T(2) * Pi<T>::v;
+    T r = v - two_pi * rint_t(v * (T(0.5) / Pi<T>::v));
+    return r <= -Pi<T>::v ? Pi<T>::v : r;
+}
+
+// FP64 link phase from the complex product, -pi mapped to +pi.
+__device__ __forceinline__ double exact_link_phase_body(double are, double aim, double bre, double bim, double hA) {
+    double s, c;
+    sincos(hA, &s, &c);
+    const double ure = c, uim = -s;
+    // (conj(a) * U) * b
+    const double tre = are * ure + aim * uim, tim = are * uim - aim * ure;
+    const double zre = tre * bre - tim * bim, zim = tre * bim + tim * bre;
+    double ang = atan2(zim, zre);
+    return ang <= -Pi<double>::v ? Pi<double>::v : ang;
+}
+static __device__ __noinline__ double exact_link_phase(double are, double aim, double bre, double bim, double hA) {
+    return exact_link_phase_body(are, aim, bre, bim, hA);
+}
+
+// The fast link phase from the two phases; `need` is set where the guard
+// asks for the FP64 product instead.
+template <typename T>
+__device__ __forceinline__ T link_chi_fast(T aa, T ab, T hA, bool &need) {
+    const T chi = wrap_pi((ab - aa) - hA);
+    need = isnan(aa) || isnan(ab) || fabs(chi) > Pi<T>::v - Guard<T>::cut || fabs(hA) > Guard<T>::big;
+    return chi;
+}
+
+// The guarded link phase from the field values at the two ends (0 if either
+// vanishes), FP64.
+template <typename T>
+__device__ __forceinline__ T link_chi_exact(cx<T> a, cx<T> b, T hA) {
+    const bool z0 = (a.re == T(0) && a.im == T(0)) || (b.re == T(0) && b.im == T(0));
+    return z0 ? T(0) : (T)exact_link_phase(a.re, a.im, b.re, b.im, (double)hA);
+}
+
+// chi + h A of a link for the fused diagnostics, or NaN where the guard asks
+// for the FP64 product (near the branch cut or |h A| above Guard::big; a NaN
+// phase, phi = 0 at an end, gives NaN by itself).
+template <typename T>
+__device__ __forceinline__ T link_value_or_nan(T aa, T ab, T hA) {
+#pragma clang fp contract(off)
+    const T chi = wrap_pi((ab - aa) - hA);
+    const bool ok = fabs(chi) <= Pi<T>::v - Guard<T>::cut && fabs(hA) <= Guard<T>::big;
+    return ok ? chi + hA : T(NAN);
+}
+
+// chi of the link from site a to site b (phases aa, ab; link hA), guarded.
+template <typename T>
+__device__ __forceinline__ T link_chi(T aa, T ab, T hA, const cx<T> *phi, uint32_t sa, uint32_t sb) {
+    bool need;
+    T chi = link_chi_fast(aa, ab, hA, need);
+    if (need) {
+        const cx<T> a = phi[sa], b = phi[sb];
+        const bool z0 = (a.re == T(0) && a.im == T(0)) || (b.re == T(0) && b.im == T(0));
+        chi = z0 ? T(0) : (T)exact_link_phase(a.re, a.im, b.re, b.im, (double)hA);
+    }
+    return chi;
+}
+
+// arg phi, NaN where phi = 0 (the winding kernels' phase)
+template <typename T>
+__device__ __forceinline__ T phase_of(cx<T> p) {
+    return (p.re == T(0) && p.im == T(0)) ? T(NAN) : atan2_t(p.im, p.re);
+}
+
+// Gauss law at n + 1/2 (Sec. II; reading R9): the divergence of E from its
+// values at the site and at x - i, the charge term g Im[conj(phi^n) Pi^{n+1/2}],
+// and their accumulation into |C| and the scale |div E| + |g rho|.  One
+// definition for every kernel that evaluates it, contraction off, so the
+// per-site terms agree bit for bit.
+template <typename T>
+__device__ __forceinline__ T gauss_div(T ex, T ex_m, T ey, T ey_m, T ez, T ez_m, T inv_h) {
+#pragma clang fp contract(off)
+    return (((ex - ex_m) + (ey - ey_m)) + (ez - ez_m)) * inv_h;
+}
+template <typename T>
+__device__ __forceinline__ T gauss_charge(T g, cx<T> f, cx<T> p) {
+#pragma clang fp contract(off)
+    return g * imc(f, p);
+}
+template <typename T>
+__device__ __forceinline__ void gauss_accumulate(T div, T grho, double &abs_acc, double &scale_acc) {
+#pragma clang fp contract(off)
+    abs_acc += (double)fabs(div - grho);
+    scale_acc += (double)fabs(div) + (double)fabs(grho);
+}
+
 // Stores of data written once per step and not re-read by this launch.
 // With NT they are streaming (non-temporal) stores that bypass L2
 // allocation, leaving L2 to the halo rows neighbouring tiles share; the

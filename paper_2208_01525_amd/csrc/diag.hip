@@ -6,11 +6,8 @@
 // Windings.  With alpha(x) = arg phi(x), the covariant link phase is
 //   chi_mu(x) = arg(conj(phi(x)) U_mu(x) phi(x+mu)) = wrap(alpha(x+mu) - alpha(x) - h A_mu(x)),
 // wrap into (-pi, pi], so one atan2 per site replaces a sincos and an atan2
-// per link.  A link whose chi lies within `guard` of the branch cut (or has
-// an endpoint with phi = 0, or |h A| too large for the precision) is
-// recomputed in FP64 from the complex product, so the windings equal an FP64
-// evaluation of the same inputs bit for bit.  The winding through the face
-// normal to rho, (mu, nu, rho) cyclic, is
+// per link (guarded near the branch cut: link_chi in device.h).  The winding
+// through the face normal to rho, (mu, nu, rho) cyclic, is
 //   W_rho(x) = rint([chi_mu(x) + chi_nu(x+mu) - chi_mu(x+nu) - chi_nu(x) + theta_mu,nu(x)] / 2 pi).
 //
 // Overlap.  When nx is a multiple of 64, the cell kernel also packs "cell
@@ -27,50 +24,44 @@ namespace {
 
 constexpr int DX = 64, DY = 4, DZ = 4;   // wind/Gauss blocks: 64 x 4 columns, DZ planes per thread
 
-template <typename T>
-struct Guard;
-template <>
-struct Guard<float> {
-    static constexpr float cut = 1e-4f, big = 1e3f;
-};
-template <>
-struct Guard<double> {
-    static constexpr double cut = 1e-9, big = 1e6;
-};
-
-template <typename T>
-__device__ __forceinline__ T wrap_pi(T v) {   // into [-pi, pi], +pi for the cut itself
-    const T two_pi = T(2) * Pi<T>::v;
-    T r = v - two_pi * rint_t(v * (T(0.5) / Pi<T>::v));
-    return r <= -Pi<T>::v ? Pi<T>::v : r;
-}
-
-// FP64 link phase from the complex product, -pi mapped to +pi.
-__device__ __noinline__ double exact_link_phase(double are, double aim, double bre, double bim, double hA) {
-    double s, c;
-    sincos(hA, &s, &c);
-    const double ure = c, uim = -s;
-    // (conj(a) * U) * b
-    const double tre = are * ure + aim * uim, tim = are * uim - aim * ure;
-    const double zre = tre * bre - tim * bim, zim = tre * bim + tim * bre;
-    double ang = atan2(zim, zre);
-    return ang <= -Pi<double>::v ? Pi<double>::v : ang;
-}
-
-// chi of the link from site a to site b (phases aa, ab; link hA), guarded.
-template <typename T>
-__device__ __forceinline__ T link_chi(T aa, T ab, T hA, const cx<T> *phi, uint32_t sa, uint32_t sb) {
-    T chi = wrap_pi((ab - aa) - hA);
-    const bool zero = isnan(aa) || isnan(ab);
-    if (zero || fabs(chi) > Pi<T>::v - Guard<T>::cut || fabs(hA) > Guard<T>::big) {
-        const cx<T> a = phi[sa], b = phi[sb];
-        const bool z0 = (a.re == T(0) && a.im == T(0)) || (b.re == T(0) && b.im == T(0));
-        chi = z0 ? T(0) : (T)exact_link_phase(a.re, a.im, b.re, b.im, (double)hA);
-    }
-    return chi;
-}
-
 __device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Windings through the three faces whose lower corner is site s (W_x: the yz
+// face, W_y: zx, W_z: xy) from the phases of the seven corners involved
+// (a0 at s, ax at s + x, ..., ayz at s + y + z), the link angles / h of the
+// nine links (A*0 at s, A*_p* at the neighbour), the guarded link phases and
+// the unwrapped plaquette angles.
+template <typename T>
+__device__ __forceinline__ void face_windings(T h, const cx<T> *P, T a0, T ax, T ay, T az, T axy, T axz, T ayz, T Ax0,
+                                              T Ay0, T Az0, T Ay_px, T Az_px, T Ax_py, T Az_py, T Ax_pz, T Ay_pz,
+                                              uint32_t s, uint32_t s_x, uint32_t s_y, uint32_t s_z, uint32_t s_xy,
+                                              uint32_t s_xz, uint32_t s_yz, int &Wx, int &Wy, int &Wz) {
+    const T inv2pi = T(0.5) / Pi<T>::v;
+    const T hx = h * Ax0, hy = h * Ay0, hz = h * Az0;
+    const T hy_px = h * Ay_px, hz_px = h * Az_px;
+    const T hx_py = h * Ax_py, hz_py = h * Az_py;
+    const T hx_pz = h * Ax_pz, hy_pz = h * Ay_pz;
+    const T chx = link_chi(a0, ax, hx, P, s, s_x);
+    const T chy = link_chi(a0, ay, hy, P, s, s_y);
+    const T chz = link_chi(a0, az, hz, P, s, s_z);
+    const T chy_px = link_chi(ax, axy, hy_px, P, s_x, s_xy);
+    const T chz_px = link_chi(ax, axz, hz_px, P, s_x, s_xz);
+    const T chx_py = link_chi(ay, axy, hx_py, P, s_y, s_xy);
+    const T chz_py = link_chi(ay, ayz, hz_py, P, s_y, s_yz);
+    const T chx_pz = link_chi(az, axz, hx_pz, P, s_z, s_xz);
+    const T chy_pz = link_chi(az, ayz, hy_pz, P, s_z, s_yz);
+    // unwrapped plaquette angles h [A_mu(x) + A_nu(x+mu) - A_mu(x+nu) - A_nu(x)]
+    const T txy = plaq(h, Ax0, Ay_px, Ax_py, Ay0);
+    const T tyz = plaq(h, Ay0, Az_py, Ay_pz, Az0);
+    const T tzx = plaq(h, Az0, Ax_pz, Az_px, Ax0);
+    Wz = (int)rint_t(((((chx + chy_px) - chx_py) - chy) + txy) * inv2pi);
+    Wx = (int)rint_t(((((chy + chz_py) - chy_pz) - chz) + tyz) * inv2pi);
+    Wy = (int)rint_t(((((chz + chx_pz) - chz_px) - chx) + tzx) * inv2pi);
+}
+
+__device__ __forceinline__ uint8_t pack_wabs(int Wx, int Wy, int Wz) {
+    return (uint8_t)(min(abs(Wx), 3) | (min(abs(Wy), 3) << 2) | (min(abs(Wz), 3) << 4));
+}
 
 }  // namespace
 
@@ -83,7 +74,7 @@ __global__ __launch_bounds__(256) void phase_kernel(Fields<T> f, T *alpha, uint3
 #pragma unroll
     for (int sec = 0; sec < 2; sec++) {
         const cx<T> p = f.phi[sec][s];
-        alpha[(size_t)sec * plane + s] = (p.re == T(0) && p.im == T(0)) ? T(NAN) : atan2_t(p.im, p.re);
+        alpha[(size_t)sec * plane + s] = phase_of(p);
     }
 }
 
@@ -102,15 +93,14 @@ uint32_t wind_blocks(const Geom &g) {
 
 template <typename T>
 __global__ __launch_bounds__(DX *DY) void wind_gauss_kernel(Geom g, Fields<T> f, Moms<T> mom, const T *alpha, T h,
-                                                            double g_p, double g_q, uint8_t *wabs, uint32_t plane,
-                                                            int8_t *signed_out, Partials part) {
+                                                            T inv_h, double g_p, double g_q, uint8_t *wabs,
+                                                            uint32_t plane, int8_t *signed_out, Partials part) {
     const int x = blockIdx.x * DX + threadIdx.x;
     const int y = blockIdx.y * DY + threadIdx.y;
     double acc[6] = {0, 0, 0, 0, 0, 0};   // gauss_abs p,q; gauss_scale p,q; wind p,q
     if (x < g.nx && y < g.ny) {
         const int xp = wrap1(x + 1, g.nx), xm = wrap1(x - 1, g.nx);
         const int yp = wrap1(y + 1, g.ny), ym = wrap1(y - 1, g.ny);
-        const T inv2pi = T(0.5) / Pi<T>::v;
         const uint32_t nx = g.nx, nxy = g.nxy;
         const int zb = blockIdx.z * DZ, z1 = min(zb + DZ, g.nz);
         // Values of plane z+1 that plane z reads are those plane z+1 reads at
@@ -152,26 +142,9 @@ __global__ __launch_bounds__(DX *DY) void wind_gauss_kernel(Geom g, Fields<T> f,
                 c_ay[sec] = ayz;
                 c_Ax[sec] = Ax_z;
                 c_Ay[sec] = Ay_z;
-                const T hx = h * Ax0, hy = h * Ay0, hz = h * Az0;
-                const T hy_px = h * Ay[s_x], hz_px = h * Az[s_x];
-                const T hx_py = h * Ax[s_y], hz_py = h * Az[s_y];
-                const T hx_pz = h * Ax_z, hy_pz = h * Ay_z;
-                const T chx = link_chi(a0, ax, hx, P, s, s_x);
-                const T chy = link_chi(a0, ay, hy, P, s, s_y);
-                const T chz = link_chi(a0, az, hz, P, s, s_z);
-                const T chy_px = link_chi(ax, axy, hy_px, P, s_x, s_xy);
-                const T chz_px = link_chi(ax, axz, hz_px, P, s_x, s_xz);
-                const T chx_py = link_chi(ay, axy, hx_py, P, s_y, s_xy);
-                const T chz_py = link_chi(ay, ayz, hz_py, P, s_y, s_yz);
-                const T chx_pz = link_chi(az, axz, hx_pz, P, s_z, s_xz);
-                const T chy_pz = link_chi(az, ayz, hy_pz, P, s_z, s_yz);
-                // unwrapped plaquette angles h [A_mu(x) + A_nu(x+mu) - A_mu(x+nu) - A_nu(x)]
-                const T txy = plaq(h, Ax0, Ay[s_x], Ax[s_y], Ay0);
-                const T tyz = plaq(h, Ay0, Az[s_y], Ay_z, Az0);
-                const T tzx = plaq(h, Az0, Ax_z, Az[s_x], Ax0);
-                const int Wz = (int)rint_t(((((chx + chy_px) - chx_py) - chy) + txy) * inv2pi);
-                const int Wx = (int)rint_t(((((chy + chz_py) - chy_pz) - chz) + tyz) * inv2pi);
-                const int Wy = (int)rint_t(((((chz + chx_pz) - chz_px) - chx) + tzx) * inv2pi);
+                int Wx, Wy, Wz;
+                face_windings(h, P, a0, ax, ay, az, axy, axz, ayz, Ax0, Ay0, Az0, Ay[s_x], Az[s_x], Ax[s_y], Az[s_y],
+                              Ax_z, Ay_z, s, s_x, s_y, s_z, s_xy, s_xz, s_yz, Wx, Wy, Wz);
                 if (signed_out) {
                     auto cl = [](int w) { return (int8_t)(w > 127 ? 127 : (w < -127 ? -127 : w)); };
                     signed_out[(size_t)(3 * sec + 0) * plane + s] = cl(Wx);
@@ -179,20 +152,17 @@ __global__ __launch_bounds__(DX *DY) void wind_gauss_kernel(Geom g, Fields<T> f,
                     signed_out[(size_t)(3 * sec + 2) * plane + s] = cl(Wz);
                     continue;
                 }
-                const int aWx = abs(Wx), aWy = abs(Wy), aWz = abs(Wz);
-                wabs[(size_t)sec * plane + s] = (uint8_t)(min(aWx, 3) | (min(aWy, 3) << 2) | (min(aWz, 3) << 4));
-                acc[4 + sec] += (double)(aWx + aWy + aWz);
+                wabs[(size_t)sec * plane + s] = pack_wabs(Wx, Wy, Wz);
+                acc[4 + sec] += (double)(abs(Wx) + abs(Wy) + abs(Wz));
 
                 // Gauss residual at n+1/2: div E^{n+1/2} - g Im[conj(phi^n) Pi^{n+1/2}]
                 const T *Ex = mom.E[sec][0], *Ey = mom.E[sec][1], *Ez = mom.E[sec][2];
                 const uint32_t s_mx = xm + nx * y + nxy * z, s_my = x + nx * ym + nxy * z;
                 const T ez0 = Ez[s], ezm = c_Ez[sec];
                 c_Ez[sec] = ez0;
-                const T div = (((Ex[s] - Ex[s_mx]) + (Ey[s] - Ey[s_my])) + (ez0 - ezm)) / h;
+                const T div = gauss_div(Ex[s], Ex[s_mx], Ey[s], Ey[s_my], ez0, ezm, inv_h);
                 const T gs = (T)(sec == 0 ? g_p : g_q);
-                const T grho = gs * imc(P[s], mom.pi[sec][s]);
-                acc[sec] += (double)fabs(div - grho);
-                acc[2 + sec] += (double)fabs(div) + (double)fabs(grho);
+                gauss_accumulate(div, gauss_charge(gs, P[s], mom.pi[sec][s]), acc[sec], acc[2 + sec]);
             }
         }
     }
@@ -203,14 +173,78 @@ __global__ __launch_bounds__(DX *DY) void wind_gauss_kernel(Geom g, Fields<T> f,
 }
 
 template <typename T>
-hipError_t launch_wind_gauss(const Geom &g, Fields<T> f, Moms<T> mom, const T *alpha, T h, const double gcoef[2],
-                             uint8_t *wabs, uint32_t plane, int8_t *signed_out, Partials part, hipStream_t st) {
+hipError_t launch_wind_gauss(const Geom &g, Fields<T> f, Moms<T> mom, const T *alpha, T h, T inv_h,
+                             const double gcoef[2], uint8_t *wabs, uint32_t plane, int8_t *signed_out, Partials part,
+                             hipStream_t st) {
     dim3 block(DX, DY, 1);
     dim3 grid((g.nx + DX - 1) / DX, (g.ny + DY - 1) / DY, (g.nz + DZ - 1) / DZ);
-    wind_gauss_kernel<T><<<grid, block, 0, st>>>(g, f, mom, alpha, h, gcoef[0], gcoef[1], wabs, plane, signed_out,
-                                                 part);
+    wind_gauss_kernel<T><<<grid, block, 0, st>>>(g, f, mom, alpha, h, inv_h, gcoef[0], gcoef[1], wabs, plane,
+                                                 signed_out, part);
     return hipGetLastError();
 }
+
+// ---------------------------------------------------------------- fix-up of the fused windings
+
+constexpr int FIX_SITES = 16;   // sites per thread of the fix-up scan (one 16-byte load per sector)
+
+uint32_t wind_fix_blocks(const Geom &g) {
+    return ((g.nxy * (uint32_t)g.nz + FIX_SITES - 1) / FIX_SITES + 255) / 256;
+}
+
+// The fused diagnostic step marks (WABS_FIX) the sites whose windings used a
+// link the guard sends to FP64; here each marked site's three faces are
+// evaluated as the post-step kernel does, its byte rewritten and its sum |W|
+// added to the SL_FIX_P / SL_FIX_Q partials (the fused kernel counted nothing
+// for it).  A thread scans 16 sites per sector with one 16-byte load (the
+// sector's byte plane is padded to a multiple of 64 sites).
+template <typename T>
+__global__ __launch_bounds__(256) void wind_fix_kernel(Geom g, Fields<T> f, T h, uint8_t *wabs, uint32_t plane,
+                                                       Partials part) {
+    const uint32_t S = g.nxy * (uint32_t)g.nz;
+    const uint32_t s0 = (blockIdx.x * 256 + threadIdx.x) * FIX_SITES;
+    double acc[2] = {0, 0};
+    if (s0 < S) {
+#pragma unroll
+        for (int sec = 0; sec < 2; sec++) {
+            uint8_t *wb = wabs + (size_t)sec * plane + s0;
+            const uint4 v = *reinterpret_cast<const uint4 *>(wb);
+            constexpr uint32_t M = 0x01010101u * WABS_FIX;
+            if (!((v.x | v.y | v.z | v.w) & M)) continue;
+            const cx<T> *P = f.phi[sec];
+            const T *Ax = f.A[sec][0], *Ay = f.A[sec][1], *Az = f.A[sec][2];
+            for (int k = 0; k < FIX_SITES; k++) {
+                const uint32_t s = s0 + k;
+                if (s >= S || !(wb[k] & WABS_FIX)) continue;
+                const int x = s % g.nx, y = (s / g.nx) % g.ny, z = s / g.nxy;
+                const uint32_t nx = g.nx, nxy = g.nxy;
+                const int xp = wrap1(x + 1, g.nx), yp = wrap1(y + 1, g.ny), zp = wrap1(z + 1, g.nz);
+                const uint32_t s_x = xp + nx * y + nxy * z, s_y = x + nx * yp + nxy * z, s_z = x + nx * y + nxy * zp;
+                const uint32_t s_xy = xp + nx * yp + nxy * z, s_xz = xp + nx * y + nxy * zp;
+                const uint32_t s_yz = x + nx * yp + nxy * zp;
+                int Wx, Wy, Wz;
+                face_windings(h, P, phase_of(P[s]), phase_of(P[s_x]), phase_of(P[s_y]), phase_of(P[s_z]),
+                              phase_of(P[s_xy]), phase_of(P[s_xz]), phase_of(P[s_yz]), Ax[s], Ay[s], Az[s], Ay[s_x],
+                              Az[s_x], Ax[s_y], Az[s_y], Ax[s_z], Ay[s_z], s, s_x, s_y, s_z, s_xy, s_xz, s_yz, Wx,
+                              Wy, Wz);
+                wb[k] = pack_wabs(Wx, Wy, Wz);
+                acc[sec] += (double)(abs(Wx) + abs(Wy) + abs(Wz));
+            }
+        }
+    }
+    block_sum_store<2, 4>(acc, part, SL_FIX_P, blockIdx.x);
+}
+
+template <typename T>
+hipError_t launch_wind_fix(const Geom &g, Fields<T> f, T h, uint8_t *wabs, uint32_t plane, Partials part,
+                           hipStream_t st) {
+    wind_fix_kernel<T><<<wind_fix_blocks(g), 256, 0, st>>>(g, f, h, wabs, plane, part);
+    return hipGetLastError();
+}
+
+template hipError_t launch_wind_fix<float>(const Geom &, Fields<float>, float, uint8_t *, uint32_t, Partials,
+                                           hipStream_t);
+template hipError_t launch_wind_fix<double>(const Geom &, Fields<double>, double, uint8_t *, uint32_t, Partials,
+                                            hipStream_t);
 
 // ---------------------------------------------------------------- cells
 
@@ -399,9 +433,10 @@ hipError_t launch_reduce(Partials part, const uint32_t *nblk_per_slot_dev, doubl
 
 template hipError_t launch_phase<float>(const Geom &, Fields<float>, float *, uint32_t, hipStream_t);
 template hipError_t launch_phase<double>(const Geom &, Fields<double>, double *, uint32_t, hipStream_t);
-template hipError_t launch_wind_gauss<float>(const Geom &, Fields<float>, Moms<float>, const float *, float,
+template hipError_t launch_wind_gauss<float>(const Geom &, Fields<float>, Moms<float>, const float *, float, float,
                                              const double[2], uint8_t *, uint32_t, int8_t *, Partials, hipStream_t);
 template hipError_t launch_wind_gauss<double>(const Geom &, Fields<double>, Moms<double>, const double *, double,
-                                              const double[2], uint8_t *, uint32_t, int8_t *, Partials, hipStream_t);
+                                              double, const double[2], uint8_t *, uint32_t, int8_t *, Partials,
+                                              hipStream_t);
 
 }  // namespace mts

@@ -52,6 +52,7 @@ struct StepCoef {
     T inv_e2h4[2];        // 1 / (e_0^2 h^4)
     T lam4[2];            // lambda_0 / 4
     T kap0;               // kappa_0
+    T gsig[2];            // Gauss-law coupling 2 e_0^2 a^{2s} (1 + delta)/(1 + omega)
 };
 
 // Reduction slots of one diagnostic record (FP64 partials per block).
@@ -59,8 +60,14 @@ enum Slot {
     SL_EPS = 0, SL_LAG, SL_KL, SL_GL, SL_KV, SL_GV,
     SL_GAUSS_ABS_P, SL_GAUSS_ABS_Q, SL_GAUSS_SCALE_P, SL_GAUSS_SCALE_Q,
     SL_WIND_P, SL_WIND_Q, SL_OV_P, SL_OV_Q,
+    SL_FIX_P, SL_FIX_Q,   // sum |W| of the sites the fused path left to the fix-up kernel
     NSLOT = 16
 };
+
+// Packed |W| byte of a site: |W_x|, |W_y|, |W_z| in two bits each; the fused
+// diagnostic step sets WABS_FIX where the fix-up kernel must evaluate the
+// site's windings.
+constexpr uint8_t WABS_FIX = 0x40;
 
 // Where the partials of one diagnostic step go.
 struct Partials {
@@ -111,10 +118,14 @@ hipError_t launch_cool_tile(const Geom &g, Fields<T> in, Fields<T> out, const St
 // XCD b mod 8 takes that XCD's next tile in x, y, z order); without it block
 // b takes tile b, the hardware's round-robin order.  Results do not depend
 // on it.
+// With diag and a non-null wabs (FP32, rows 4, 5 or 8, mom_out a different
+// copy from mom) the windings of the input fields (packed |W| into wabs) and
+// the Gauss residual are computed in the same pass, into partial slots
+// SL_EPS .. SL_WIND_Q; alpha is then unused.
 template <typename T>
 hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, Moms<T> mom_out,
-                            const StepCoef<T> &c, bool diag, Partials part, TileShape ts, T *alpha, uint32_t plane,
-                            bool nt, bool pf, bool xcd, hipStream_t st);
+                            const StepCoef<T> &c, bool diag, Partials part, TileShape ts, T *alpha, uint8_t *wabs,
+                            uint32_t plane, bool nt, bool pf, bool xcd, hipStream_t st);
 
 // Two steps in one sweep (temporal blocking, FP32): reads fields n from
 // `in` and momenta n - 1/2 from `min_`, writes fields n + 2 to `out` and
@@ -155,9 +166,18 @@ hipError_t launch_phase(const Geom &g, Fields<T> f, T *alpha, uint32_t plane, hi
 // If `signed_out` is non-null the signed windings go there as int8[6][plane]
 // and nothing else is written.
 template <typename T>
-hipError_t launch_wind_gauss(const Geom &g, Fields<T> f, Moms<T> mom, const T *alpha, T h, const double gcoef[2],
-                             uint8_t *wabs, uint32_t plane, int8_t *signed_out, Partials part, hipStream_t st);
+hipError_t launch_wind_gauss(const Geom &g, Fields<T> f, Moms<T> mom, const T *alpha, T h, T inv_h,
+                             const double gcoef[2], uint8_t *wabs, uint32_t plane, int8_t *signed_out, Partials part,
+                             hipStream_t st);
 uint32_t wind_blocks(const Geom &g);
+
+// Sites the fused diagnostic step marked WABS_FIX: their windings evaluated
+// with the guarded link phases of the post-step kernel, bytes rewritten,
+// sum |W| into slots SL_FIX_P / SL_FIX_Q (wind_fix_blocks partials).
+uint32_t wind_fix_blocks(const Geom &g);
+template <typename T>
+hipError_t launch_wind_fix(const Geom &g, Fields<T> f, T h, uint8_t *wabs, uint32_t plane, Partials part,
+                           hipStream_t st);
 
 // Cell values from packed |W| (cells[2][plane] bytes) and, when nx is a
 // multiple of 64, the 64-cell occupancy words bits[2][overlap_words]; then

@@ -48,6 +48,29 @@ struct SiteIn {
     T a[3];                            // A^n (h A is the link angle)
 };
 
+// Magnetic force on a link, -h^-3 [(s1 - s2) + (s3 - s4)] from the sines of
+// the two plaquettes at the link's site and the two at x - j (Sec. III E
+// kick, the divergence form of reading R3).
+template <typename T>
+__device__ __forceinline__ T mag_force(const StepCoef<T> &c, T s1, T s2, T s3, T s4) {
+#pragma clang fp contract(off)
+    return -c.inv_h3 * ((s1 - s2) + (s3 - s4));
+}
+
+// The current 2 e^2 a^{2s} h^-1 Im[conj(phi) U phi(x+i)] (w = U phi(x+i)).
+template <typename T>
+__device__ __forceinline__ T current(const StepCoef<T> &c, int sec, cx<T> f, cx<T> w) {
+#pragma clang fp contract(off)
+    return c.cur[sec] * imc(f, w);
+}
+
+// The damped gauge kick of one link: (1+omega) E' = (1-omega) E + k (M + J).
+template <typename T>
+__device__ __forceinline__ T e_kick(const StepCoef<T> &c, T e0, T M, T J) {
+#pragma clang fp contract(off)
+    return fma_t(c.cE, e0, c.kE * (M + J));
+}
+
 template <typename T>
 struct SiteOut {
     cx<T> p1;                          // Pi^{n+1/2}   (COOL: the force)
@@ -89,18 +112,18 @@ __device__ __forceinline__ SiteOut<T> site_update(const StepCoef<T> &c, int sec,
     r.fn.re = fma_t(c.k, r.p1.re, f.re);
     r.fn.im = fma_t(c.k, r.p1.im, f.im);
 
-    const T Mx = -c.inv_h3 * ((q.sxy - q.sxy_my) + (q.sxz - q.sxz_mz));
-    const T My = -c.inv_h3 * ((q.sxy_mx - q.sxy) + (q.syz - q.syz_mz));
-    const T Mz = -c.inv_h3 * ((q.sxz_mx - q.sxz) + (q.syz_my - q.syz));
-    const T Jx = c.cur[sec] * imc(f, r.wx), Jy = c.cur[sec] * imc(f, r.wy), Jz = c.cur[sec] * imc(f, r.wz);
+    const T Mx = mag_force(c, q.sxy, q.sxy_my, q.sxz, q.sxz_mz);
+    const T My = mag_force(c, q.sxy_mx, q.sxy, q.syz, q.syz_mz);
+    const T Mz = mag_force(c, q.sxz_mx, q.sxz, q.syz_my, q.syz);
+    const T Jx = current(c, sec, f, r.wx), Jy = current(c, sec, f, r.wy), Jz = current(c, sec, f, r.wz);
     if constexpr (COOL) {
         r.e1[0] = Mx + Jx;
         r.e1[1] = My + Jy;
         r.e1[2] = Mz + Jz;
     } else {
-        r.e1[0] = fma_t(c.cE, q.e0[0], c.kE * (Mx + Jx));
-        r.e1[1] = fma_t(c.cE, q.e0[1], c.kE * (My + Jy));
-        r.e1[2] = fma_t(c.cE, q.e0[2], c.kE * (Mz + Jz));
+        r.e1[0] = e_kick(c, q.e0[0], Mx, Jx);
+        r.e1[1] = e_kick(c, q.e0[1], My, Jy);
+        r.e1[2] = e_kick(c, q.e0[2], Mz, Jz);
     }
 #pragma unroll
     for (int i = 0; i < 3; i++) r.an[i] = fma_t(c.k, r.e1[i], q.a[i]);

@@ -18,6 +18,8 @@
 // Workgroups are numbered so that each XCD (workgroups are dealt round-robin
 // to the 8 XCDs) processes one contiguous run of tiles, keeping the halo
 // rows shared by neighbouring tiles inside one L2.
+#include <type_traits>
+
 #include "device.h"
 #include "kernels.h"
 #include "site.h"
@@ -33,31 +35,85 @@ __device__ __forceinline__ int wrapi(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
-// LDS quantities per sector
+// LDS quantities per sector; the fused diagnostic variant adds the phase of
+// the next plane, the link values c = chi + h A of the plane and the new
+// electric fields E_x, E_y (for the divergence at x + i)
 enum Q { Q_FR, Q_FI, Q_UXR, Q_UXI, Q_UYR, Q_UYI, Q_UZR, Q_UZI, Q_SXY, Q_SXZ, Q_SYZ, NQ };
+enum QF { Q_AN = NQ, Q_CX, Q_CY, Q_CZ, Q_EX, Q_EY, NQF };
 
-template <typename T, int TY>
+template <typename T, int TY, int NQX = NQ>
 struct Lds {
-    T v[2][NQ][(TY + 2) * LW];
+    T v[2][NQX][(TY + 2) * LW];
 };
 
-template <typename T, int TY>
-__device__ __forceinline__ cx<T> ldc(const Lds<T, TY> &L, int sec, int q, int i) {
+template <typename T, int TY, int NQX>
+__device__ __forceinline__ cx<T> ldc(const Lds<T, TY, NQX> &L, int sec, int q, int i) {
     return cx<T>{L.v[sec][q][i], L.v[sec][q + 1][i]};
 }
 
+// Per-thread LDS slots of the fused diagnostics (interior threads, index
+// w * 64 + lane): the FP64 sums of the Gauss residual and of the windings,
+// and the new E_z and charge term of the plane just updated, which the
+// divergence reads after the plane's last barrier.  Kept out of registers.
+template <typename T, int TY>
+struct FusedLds {
+    double acc[4][64 * TY];   // Gauss |C| p, q; scale p, q
+    int wsum[2][64 * TY];     // sum |W| p, q
+    T ez[2][64 * TY];
+    T gr[2][64 * TY];
+};
+template <typename T, int TY>
+struct NoFusedLds {};
+
+// c = chi + h A, the sum rounded on its own
+template <typename T>
+__device__ __forceinline__ T link_value(T chi, T hA) {
+#pragma clang fp contract(off)
+    return chi + hA;
+}
+template <typename T>
+__device__ __forceinline__ T link_angle(T h, T A) {
+#pragma clang fp contract(off)
+    return h * A;
+}
+
 }  // namespace
+
+// Accumulators of one thread's integer-time sums: the six of the update
+// (energy, Lagrangian, the four velocity sums), then with the fused
+// diagnostics the Gauss residual sums (|C| and scale, per sector) and the
+// winding sums (per sector), in the order of the reduction slots.
+constexpr int NACC_FUSED = SL_WIND_Q + 1;
 
 // One tile (64 x TY columns, planes [Z0, Z0 + TZ)) of one box; accumulates the
 // integer-time sums of its interior sites into acc when DIAG.  With COOL the
 // fields move along their forces (one forward-Euler step of the cooling
 // flow, coefficients set by the caller) and the momenta are neither read nor
 // written.
-template <typename T, bool DIAG, int TY, bool NT, bool COOL = false, int PF = 0>
+//
+// FUSE (with DIAG): the windings and the Gauss residual of the step's input
+// fields are computed here as well, and no phase is stored.  Per plane z,
+// every thread stages the phase alpha(z+1) of its site; then it forms the
+// link values c_mu = chi_mu + h A_mu of its links at z (c_z) and z+1 (c_x,
+// c_y, carried to the next plane), stages those of z, and the interior
+// threads take the windings through the three faces at their site,
+//   W_z = rint[(c_x(x) + c_y(x+x) - c_x(x+y) - c_y(x)) / 2 pi]  (and cyclic),
+// with the guard of link_chi, so they equal the post-step kernel's bit for
+// bit.  The Gauss residual C = div E^{n+1/2} - g Im[conj(phi^n) Pi^{n+1/2}]
+// needs the new E at x - i: the interior threads stage their E_x, E_y; the
+// halo column x0 - 1 and row y0 - 1 recompute theirs (E_x and E_y only, with
+// the same arithmetic as their owning tile), and at the plane below the tile
+// the interior threads recompute E_z.  Those recomputations read E^{n-1/2} of
+// sites other tiles update, so FUSE needs the momenta written out of place
+// (mom_out a different copy from mom).
+template <typename T, bool DIAG, int TY, bool NT, bool COOL = false, int PF = 0, bool FUSE = false>
 __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, const Fields<T> &out,
                                           const Moms<T> &mom, const Moms<T> &mom_out,
                                           const StepCoef<T> &c, int X0, int Y0, int Z0, int TZ,
-                                          Lds<T, TY> &L, double (&acc)[6], T *alpha, uint32_t plane) {
+                                          Lds<T, TY, FUSE ? NQF : NQ> &L, double (&acc)[FUSE ? NACC_FUSED : 6],
+                                          T *alpha, uint8_t *wabs, uint32_t plane,
+                                          typename std::conditional<FUSE, FusedLds<T, TY>, NoFusedLds<T, TY>>::type &FL) {
+    static_assert(!FUSE || (DIAG && !COOL), "fused diagnostics belong to diagnostic steps");
     constexpr int R = TY + 2;
 
     // ---- which site of the tile this thread holds
@@ -92,6 +148,11 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
     const int lxp = row * LW + min(col + 1, LW - 1), lyp = min(row + 1, R - 1) * LW + col;
     const int lxm = row * LW + max(col - 1, 0), lym = max(row - 1, 0) * LW + col;
 
+    // fused diagnostics: the halo sites whose new E_x (column x0 - 1) or E_y
+    // (row y0 - 1) the divergence of an interior site needs
+    const bool edge_x = FUSE && owner && col == 0 && row >= 1 && row <= TY && gy < g.ny;
+    const bool edge_y = FUSE && w == TY && gx < g.nx;
+
     const int zbeg = Z0, zend = min(Z0 + TZ, g.nz);
 
     // registers: plane z (cur), z+1 (nxt), z-1 (prv)
@@ -99,6 +160,9 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
     T cA[2][3], nA[2][3];
     cx<T> cU[2][3], nU[2][3], pUz[2];
     T psxz[2], psyz[2];
+    // fused: alpha(z); c_x(z), c_y(z); E_z^{n+1/2}(z-1)
+    T alc[2], cxc[2], cyc[2], ezp[2];
+    const int it = w * 64 + lx;            // interior thread's slot in FL
     auto load_raw = [&](int zz, cx<T> (&f)[2], T (&A)[2][3]) {
         const uint32_t s = colidx + g.nxy * (uint32_t)zz;
 #pragma unroll
@@ -130,6 +194,21 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
 
     load_raw(wrapi(zbeg - 1, g.nz), cf, cA);
     make_U(cA, cU);
+    if constexpr (FUSE) {
+#pragma unroll
+        for (int sec = 0; sec < 2; sec++) {
+            alc[sec] = phase_of(cf[sec]);
+            cxc[sec] = T(0);
+            cyc[sec] = T(0);
+            ezp[sec] = T(0);
+        }
+        if (interior) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) FL.acc[q][it] = 0.0;
+            FL.wsum[0][it] = 0;
+            FL.wsum[1][it] = 0;
+        }
+    }
     if constexpr (PF >= 1) {
         load_raw(wrapi(zbeg, g.nz), rf, rA);
 #pragma unroll
@@ -143,6 +222,7 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
     for (int z = zbeg - 1; z < zend; z++) {
         const bool upd = interior && z >= zbeg;
         const int zz = wrapi(z, g.nz);
+        const int zn = wrapi(z + 1, g.nz);
         const uint32_t s = colidx + g.nxy * (uint32_t)zz;
         cx<T> p0[2];
         T e0[2][3];
@@ -168,12 +248,25 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
             }
             make_U(nA, nU);
         } else {
-            load_raw(wrapi(z + 1, g.nz), nf, nA);
+            load_raw(zn, nf, nA);
             make_U(nA, nU);
             if (upd && !COOL) load_mom(s, p0, e0);
         }
+        // fused: E^{n-1/2} of the halo components this thread recomputes
+        T eh[2] = {T(0), T(0)};
+        if constexpr (FUSE) {
+            const int comp = edge_x ? 0 : (edge_y ? 1 : 2);
+            if ((edge_x || edge_y) && z >= zbeg) {
+#pragma unroll
+                for (int sec = 0; sec < 2; sec++) eh[sec] = mom.E[sec][comp][s];
+            } else if (interior && z == zbeg - 1) {
+#pragma unroll
+                for (int sec = 0; sec < 2; sec++) eh[sec] = mom.E[sec][2][s];
+            }
+        }
 
-        // stage phi and U of plane z
+        // stage phi and U of plane z (fused: and the phase of plane z+1)
+        T aln[2] = {T(0), T(0)};
         if (owner) {
 #pragma unroll
             for (int sec = 0; sec < 2; sec++) {
@@ -183,6 +276,10 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                 for (int i = 0; i < 3; i++) {
                     L.v[sec][Q_UXR + 2 * i][li] = cU[sec][i].re;
                     L.v[sec][Q_UXI + 2 * i][li] = cU[sec][i].im;
+                }
+                if constexpr (FUSE) {
+                    aln[sec] = phase_of(nf[sec]);
+                    L.v[sec][Q_AN][li] = aln[sec];
                 }
             }
         }
@@ -201,7 +298,71 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                 L.v[sec][Q_SYZ][li] = sn[sec][2];
             }
         }
+        // fused: link values c of plane z+1 (x and y links, where the
+        // neighbour lies in the tile) and of plane z (z link); stage those of z
+        T cxn[2], cyn[2], czc[2];
+        if constexpr (FUSE) {
+            // a link the guard flags (near the branch cut, at a zero of the
+            // field, or a large angle) gets the value NaN: every face it
+            // bounds then sums to NaN and its site is left to the fix-up
+            // kernel, which takes the FP64 product there
+#pragma unroll
+            for (int sec = 0; sec < 2; sec++) {
+                cxn[sec] = link_value_or_nan(aln[sec], L.v[sec][Q_AN][lxp], link_angle(c.h, nA[sec][0]));
+                cyn[sec] = link_value_or_nan(aln[sec], L.v[sec][Q_AN][lyp], link_angle(c.h, nA[sec][1]));
+                czc[sec] = link_value_or_nan(alc[sec], aln[sec], link_angle(c.h, cA[sec][2]));
+                if (owner) {
+                    L.v[sec][Q_CX][li] = cxc[sec];
+                    L.v[sec][Q_CY][li] = cyc[sec];
+                    L.v[sec][Q_CZ][li] = czc[sec];
+                }
+            }
+        }
         __syncthreads();
+
+        if constexpr (FUSE) {
+            if (upd) {
+                // windings through the three faces at the site (lower corner x)
+                const T inv2pi = T(0.5) / Pi<T>::v;
+#pragma unroll
+                for (int sec = 0; sec < 2; sec++) {
+                    const T sz = (((cxc[sec] + L.v[sec][Q_CY][lxp]) - L.v[sec][Q_CX][lyp]) - cyc[sec]) * inv2pi;
+                    const T sx = (((cyc[sec] + L.v[sec][Q_CZ][lyp]) - cyn[sec]) - czc[sec]) * inv2pi;
+                    const T sy = (((czc[sec] + cxn[sec]) - L.v[sec][Q_CZ][lxp]) - cxc[sec]) * inv2pi;
+                    uint8_t byte = WABS_FIX;
+                    if (!(isnan(sz) || isnan(sx) || isnan(sy))) {
+                        const int aWx = abs((int)rint_t(sx)), aWy = abs((int)rint_t(sy)), aWz = abs((int)rint_t(sz));
+                        byte = (uint8_t)(min(aWx, 3) | (min(aWy, 3) << 2) | (min(aWz, 3) << 4));
+                        FL.wsum[sec][it] += aWx + aWy + aWz;
+                    }
+                    st_stream<NT>(wabs + (size_t)sec * plane + s, byte);
+                }
+            } else if (edge_x || edge_y) {
+                if (z >= zbeg) {
+                    // the halo's new E_x (column x0 - 1) or E_y (row y0 - 1), as its own tile computes it
+#pragma unroll
+                    for (int sec = 0; sec < 2; sec++) {
+                        T e;
+                        if (edge_x) {
+                            const T M = mag_force(c, sn[sec][0], L.v[sec][Q_SXY][lym], sn[sec][1], psxz[sec]);
+                            e = e_kick(c, eh[sec], M, current(c, sec, cf[sec], cmul(cU[sec][0], ldc(L, sec, Q_FR, lxp))));
+                            L.v[sec][Q_EX][li] = e;
+                        } else {
+                            const T M = mag_force(c, L.v[sec][Q_SXY][lxm], sn[sec][0], sn[sec][2], psyz[sec]);
+                            e = e_kick(c, eh[sec], M, current(c, sec, cf[sec], cmul(cU[sec][1], ldc(L, sec, Q_FR, lyp))));
+                            L.v[sec][Q_EY][li] = e;
+                        }
+                    }
+                }
+            } else if (interior && z == zbeg - 1) {
+                // E_z^{n+1/2} of the plane below the tile, for the divergence at its first plane
+#pragma unroll
+                for (int sec = 0; sec < 2; sec++) {
+                    const T M = mag_force(c, L.v[sec][Q_SXZ][lxm], sn[sec][1], L.v[sec][Q_SYZ][lym], sn[sec][2]);
+                    ezp[sec] = e_kick(c, eh[sec], M, current(c, sec, cf[sec], cmul(cU[sec][2], nf[sec])));
+                }
+            }
+        }
 
         if (upd) {
             T Kd = 0, Gd = 0, Kg = 0, Bg = 0, mod2[2] = {0, 0};
@@ -265,14 +426,19 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                     Bg += c.inv_e2h4[sec] * (((T(1) - cs[sec][0]) + (T(1) - cs[sec][1])) + (T(1) - cs[sec][2]));
                     mod2[sec] = r.m2;
                 }
+                if constexpr (FUSE) {
+                    L.v[sec][Q_EX][li] = r.e1[0];
+                    L.v[sec][Q_EY][li] = r.e1[1];
+                    FL.ez[sec][it] = r.e1[2];
+                    FL.gr[sec][it] = gauss_charge(c.gsig[sec], cf[sec], r.p1);
+                }
             }
             if constexpr (DIAG) {
-                // phase of phi^n for the winding kernel (NaN where phi = 0)
+                if constexpr (!FUSE) {
+                    // phase of phi^n for the winding kernel (NaN where phi = 0)
 #pragma unroll
-                for (int sec = 0; sec < 2; sec++) {
-                    const cx<T> f = cf[sec];
-                    const T al = (f.re == T(0) && f.im == T(0)) ? T(NAN) : atan2_t(f.im, f.re);
-                    st_stream<NT>(alpha + (size_t)sec * plane + s, al);
+                    for (int sec = 0; sec < 2; sec++)
+                        st_stream<NT>(alpha + (size_t)sec * plane + s, phase_of(cf[sec]));
                 }
                 const T dp = mod2[0] - c.sig2[0], dq = mod2[1] - c.sig2[1];
                 const T Vint = c.kap0 * dp * dq;
@@ -290,6 +456,29 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
         }
         __syncthreads();   // LDS of plane z is reused by plane z+1
 
+        if constexpr (FUSE) {
+            if (upd) {
+                // Gauss residual at n + 1/2: div E^{n+1/2} - g Im[conj(phi^n) Pi^{n+1/2}]
+#pragma unroll
+                for (int sec = 0; sec < 2; sec++) {
+                    const T ez = FL.ez[sec][it];
+                    const T div = gauss_div(L.v[sec][Q_EX][li], L.v[sec][Q_EX][lxm], L.v[sec][Q_EY][li],
+                                            L.v[sec][Q_EY][lym], ez, ezp[sec], c.inv_h);
+                    double ga = FL.acc[sec][it], gsc = FL.acc[2 + sec][it];
+                    gauss_accumulate(div, FL.gr[sec][it], ga, gsc);
+                    FL.acc[sec][it] = ga;
+                    FL.acc[2 + sec][it] = gsc;
+                    ezp[sec] = ez;
+                }
+            }
+#pragma unroll
+            for (int sec = 0; sec < 2; sec++) {
+                alc[sec] = aln[sec];
+                cxc[sec] = cxn[sec];
+                cyc[sec] = cyn[sec];
+            }
+        }
+
         // rotate registers
 #pragma unroll
         for (int sec = 0; sec < 2; sec++) {
@@ -305,21 +494,28 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
             }
         }
     }
+    if constexpr (FUSE) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) acc[SL_GAUSS_ABS_P + q] = interior ? FL.acc[q][it] : 0.0;
+        acc[SL_WIND_P] = interior ? (double)FL.wsum[0][it] : 0.0;
+        acc[SL_WIND_Q] = interior ? (double)FL.wsum[1][it] : 0.0;
+    }
 }
 
-template <typename T, bool DIAG, int TY, bool NT, int PF>
+template <typename T, bool DIAG, int TY, bool NT, int PF, bool FUSE>
 __global__ __launch_bounds__(64 * (TY + 3)) void step_tile_kernel(Geom g, Fields<T> in, Fields<T> out, Moms<T> mom,
                                                                   Moms<T> mom_out,
                                                                   StepCoef<T> c, Partials part, int TZ, int ntx,
-                                                                  int nty, int ntz, T *alpha, uint32_t plane,
-                                                                  int xcd) {
-    __shared__ Lds<T, TY> L;
+                                                                  int nty, int ntz, T *alpha, uint8_t *wabs,
+                                                                  uint32_t plane, int xcd) {
+    __shared__ Lds<T, TY, FUSE ? NQF : NQ> L;
+    __shared__ typename std::conditional<FUSE, FusedLds<T, TY>, NoFusedLds<T, TY>>::type FL;
     const uint32_t t = xcd ? xcd_order(blockIdx.x, (uint32_t)(ntx * nty * ntz)) : blockIdx.x;
     const int tx = t % ntx, ty_ = (t / ntx) % nty, tz = t / (ntx * nty);
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    tile_step<T, DIAG, TY, NT, false, PF>(g, in, out, mom, mom_out, c, tx * 64, ty_ * TY, tz * TZ, TZ, L, acc, alpha,
-                                          plane);
-    if constexpr (DIAG) block_sum_store<6, TY + 3>(acc, part, SL_EPS, t);
+    double acc[FUSE ? NACC_FUSED : 6] = {};
+    tile_step<T, DIAG, TY, NT, false, PF, FUSE>(g, in, out, mom, mom_out, c, tx * 64, ty_ * TY, tz * TZ, TZ, L, acc,
+                                                alpha, wabs, plane, FL);
+    if constexpr (DIAG) block_sum_store<FUSE ? NACC_FUSED : 6, TY + 3>(acc, part, SL_EPS, t);
 }
 
 // Ensemble of boxes in one launch: the blocks of box k are [blk0[k], blk0[k+1])
@@ -359,8 +555,9 @@ __global__ __launch_bounds__(64 * (TY + 3)) void step_tile_batch_kernel(const Ba
         }
     }
     double acc[6] = {0, 0, 0, 0, 0, 0};
+    NoFusedLds<T, TY> nf;
     tile_step<T, DIAG, TY, NT>(bx.g, fin, fout, mom, mom_out, coef[lo], tx * 64, ty_ * TY, tz * bx.tz, bx.tz, L, acc,
-                               as_global(bx.alpha), bx.plane);
+                               as_global(bx.alpha), nullptr, bx.plane, nf);
     if constexpr (DIAG) {
         Partials part = bx.part;
         part.base = as_global(part.base);
@@ -377,7 +574,9 @@ __global__ __launch_bounds__(64 * (TY + 3)) void cool_tile_kernel(Geom g, Fields
     const int tx = t % ntx, ty_ = (t / ntx) % nty, tz = t / (ntx * nty);
     double acc[6] = {0, 0, 0, 0, 0, 0};
     const Moms<T> none{};
-    tile_step<T, false, TY, true, true>(g, in, out, none, none, c, tx * 64, ty_ * TY, tz * TZ, TZ, L, acc, nullptr, 0);
+    NoFusedLds<T, TY> nf;
+    tile_step<T, false, TY, true, true>(g, in, out, none, none, c, tx * 64, ty_ * TY, tz * TZ, TZ, L, acc, nullptr,
+                                        nullptr, 0, nf);
 }
 
 template <typename T>
@@ -420,34 +619,47 @@ uint32_t tile_blocks(const Geom &g, TileShape ts) {
 template <typename T, int TY>
 static hipError_t launch_ty(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, Moms<T> mom_out,
                             const StepCoef<T> &c, bool diag,
-                            Partials part, int tz, T *alpha, uint32_t plane, bool nt, bool pf, bool xcd,
-                            hipStream_t st) {
+                            Partials part, int tz, T *alpha, uint8_t *wabs, uint32_t plane, bool nt, bool pf,
+                            bool xcd, hipStream_t st) {
     const int ntx = (g.nx + 63) / 64, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + tz - 1) / tz;
     dim3 block(64, TY + 3, 1);
     dim3 grid((unsigned)(ntx * nty * ntz), 1, 1);
-#define MTS_TILE_LAUNCH(D, N, F) \
-    step_tile_kernel<T, D, TY, N, F><<<grid, block, 0, st>>>(g, in, out, mom, mom_out, c, part, tz, ntx, nty, ntz, \
-                                                             alpha, plane, xcd ? 1 : 0)
+#define MTS_TILE_LAUNCH(D, N, F, FU) \
+    step_tile_kernel<T, D, TY, N, F, FU><<<grid, block, 0, st>>>(g, in, out, mom, mom_out, c, part, tz, ntx, nty, \
+                                                                 ntz, alpha, wabs, plane, xcd ? 1 : 0)
     if (diag) {
         // FP32 diagnostic steps always load the fields one plane further
         // ahead: at the row counts they run with it costs no occupancy and
         // saves about 5 % (512^3: 4.82 against 5.08 ms).  The FP64 variant
         // is at its register limit already.  Diagnostic steps run at most 8
         // rows in FP32 and on the per-site kernel in FP64, so the shapes
-        // only plain steps use have no diagnostic variant.
+        // only plain steps use have no diagnostic variant.  With wabs the
+        // windings and the Gauss residual are fused in (FP32; momenta out of
+        // place).
         constexpr int DPF = sizeof(T) == 4 ? 1 : 0;
         if constexpr (TY == 13 || (TY == 5 && sizeof(T) == 8)) {
             return hipErrorNotSupported;
         } else {
-            if (nt) MTS_TILE_LAUNCH(true, true, DPF);
-            else MTS_TILE_LAUNCH(true, false, DPF);
+            if (wabs) {
+                if constexpr (sizeof(T) == 4 && TY != 12) {
+                    if (mom.pi[0] == mom_out.pi[0]) return hipErrorInvalidValue;
+                    // (no deeper load pipeline: its registers would spill at 8 rows)
+                    if (nt) MTS_TILE_LAUNCH(true, true, 0, true);
+                    else MTS_TILE_LAUNCH(true, false, 0, true);
+                } else {
+                    return hipErrorNotSupported;
+                }
+            } else {
+                if (nt) MTS_TILE_LAUNCH(true, true, DPF, false);
+                else MTS_TILE_LAUNCH(true, false, DPF, false);
+            }
         }
     } else if (pf) {
-        if (nt) MTS_TILE_LAUNCH(false, true, 1);
-        else MTS_TILE_LAUNCH(false, false, 1);
+        if (nt) MTS_TILE_LAUNCH(false, true, 1, false);
+        else MTS_TILE_LAUNCH(false, false, 1, false);
     } else {
-        if (nt) MTS_TILE_LAUNCH(false, true, 0);
-        else MTS_TILE_LAUNCH(false, false, 0);
+        if (nt) MTS_TILE_LAUNCH(false, true, 0, false);
+        else MTS_TILE_LAUNCH(false, false, 0, false);
     }
 #undef MTS_TILE_LAUNCH
     return hipGetLastError();
@@ -456,20 +668,23 @@ static hipError_t launch_ty(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> 
 template <typename T>
 hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> mom, Moms<T> mom_out,
                             const StepCoef<T> &c, bool diag,
-                            Partials part, TileShape ts, T *alpha, uint32_t plane, bool nt, bool pf, bool xcd,
-                            hipStream_t st) {
+                            Partials part, TileShape ts, T *alpha, uint8_t *wabs, uint32_t plane, bool nt, bool pf,
+                            bool xcd, hipStream_t st) {
+#define MTS_TY(TYV) \
+    launch_ty<T, TYV>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, wabs, plane, nt, pf, xcd, st)
     switch (ts.ty) {
-        case 4: return launch_ty<T, 4>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, xcd, st);
-        case 8: return launch_ty<T, 8>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, xcd, st);
-        case 5: return launch_ty<T, 5>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, xcd, st);
-        case 12: return launch_ty<T, 12>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, xcd, st);
+        case 4: return MTS_TY(4);
+        case 8: return MTS_TY(8);
+        case 5: return MTS_TY(5);
+        case 12: return MTS_TY(12);
         case 13:
             if constexpr (sizeof(T) == 4)
-                return launch_ty<T, 13>(g, in, out, mom, mom_out, c, diag, part, ts.tz, alpha, plane, nt, pf, xcd, st);
+                return MTS_TY(13);
             else
                 return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
+#undef MTS_TY
 }
 
 template <typename T>
@@ -521,10 +736,10 @@ template hipError_t launch_step_tile_batch<double>(const BatchBox<double> *, int
                                                    const StepCoef<double> *, bool, int, bool, bool, hipStream_t);
 
 template hipError_t launch_step_tile<float>(const Geom &, Fields<float>, Fields<float>, Moms<float>, Moms<float>,
-                                            const StepCoef<float> &, bool, Partials, TileShape, float *, uint32_t,
-                                            bool, bool, bool, hipStream_t);
+                                            const StepCoef<float> &, bool, Partials, TileShape, float *, uint8_t *,
+                                            uint32_t, bool, bool, bool, hipStream_t);
 template hipError_t launch_step_tile<double>(const Geom &, Fields<double>, Fields<double>, Moms<double>, Moms<double>,
-                                             const StepCoef<double> &, bool, Partials, TileShape, double *, uint32_t,
-                                             bool, bool, bool, hipStream_t);
+                                             const StepCoef<double> &, bool, Partials, TileShape, double *, uint8_t *,
+                                             uint32_t, bool, bool, bool, hipStream_t);
 
 }  // namespace mts

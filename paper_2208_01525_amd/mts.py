@@ -20,7 +20,7 @@ NOALLOC_MAX_SITES = 8192        # MTS_NOALLOC_MAX_SITES of include/mts.h
 
 EXPORTS = ("mts_state_bytes", "mts_create", "mts_destroy", "mts_init_fields", "mts_step", "mts_cool", "mts_diagnostics",
            "mts_get_fields", "mts_set_fields", "mts_get_windings", "mts_get_cells", "mts_get_sites", "mts_get_sites_noalloc", "mts_segments", "mts_set_tile", "mts_get_tile", "mts_set_streaming_stores", "mts_bandwidth_probe", "mts_get_streaming_stores", "mts_autotune", "mts_timing_enable",
-           "mts_timing_read", "mts_set_time_blocking", "mts_get_time_blocking", "mts_set_prefetch", "mts_get_prefetch", "mts_set_momentum_pingpong", "mts_get_momentum_pingpong", "mts_set_tile_order", "mts_get_tile_order", "mts_last_error", "mts_strerror",
+           "mts_timing_read", "mts_set_time_blocking", "mts_get_time_blocking", "mts_set_prefetch", "mts_get_prefetch", "mts_set_fused_diagnostics", "mts_get_fused_diagnostics", "mts_set_momentum_pingpong", "mts_get_momentum_pingpong", "mts_set_tile_order", "mts_get_tile_order", "mts_last_error", "mts_strerror",
            "mts_batch_state_bytes", "mts_batch_create", "mts_batch_destroy", "mts_batch_size",
            "mts_batch_init_fields", "mts_batch_step", "mts_batch_diagnostics", "mts_batch_get_fields",
            "mts_batch_set_fields", "mts_batch_set_tile", "mts_batch_set_streaming_stores", "mts_batch_get_streaming_stores", "mts_batch_set_momentum_pingpong",
@@ -130,6 +130,8 @@ def load():
     L.mts_set_time_blocking.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.mts_get_time_blocking.argtypes = [vp, i32p, i32p, i32p]
     L.mts_set_prefetch.argtypes = [vp, ctypes.c_int32]
+    L.mts_set_fused_diagnostics.argtypes = [vp, ctypes.c_int32]
+    L.mts_get_fused_diagnostics.argtypes = [vp, i32p]
     L.mts_set_momentum_pingpong.argtypes = [vp, ctypes.c_int32]
     L.mts_get_momentum_pingpong.argtypes = [vp, i32p]
     L.mts_set_tile_order.argtypes = [vp, ctypes.c_int32]
@@ -357,6 +359,15 @@ class Lattice:
         v = ctypes.c_int32()
         self._check(self.L.mts_get_prefetch(self.ctx, ctypes.byref(v)))
         return bool(v.value)
+
+    def set_fused_diagnostics(self, rows):
+        """Rows of the fused diagnostic tile (4, 5 or 8), or 0 for the post-step kernels."""
+        self._check(self.L.mts_set_fused_diagnostics(self.ctx, int(rows)))
+
+    def get_fused_diagnostics(self):
+        v = ctypes.c_int32()
+        self._check(self.L.mts_get_fused_diagnostics(self.ctx, ctypes.byref(v)))
+        return v.value
 
     def get_time_blocking(self):
         n, ty, tz = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

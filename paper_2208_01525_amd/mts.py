@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmts.so")
+# MTS_LIBRARY names another build of the same library (the sanitizer test
+# loads a host-sanitized build this way)
+LIB_PATH = os.environ.get("MTS_LIBRARY") or os.path.join(_HERE, "libmts.so")
 
 MTS_OK, MTS_EINVAL, MTS_EUNSTABLE, MTS_ENOMEM, MTS_EHIP, MTS_ENONFINITE = 0, -1, -2, -3, -4, -5
 MTS_FP32, MTS_FP64 = 1, 2

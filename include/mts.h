@@ -400,6 +400,15 @@ int mts_batch_get_momentum_pingpong(const mts_batch *b, int32_t *on);
 
 /* Tile order of the batched launch, as mts_set_tile_order (over the
  * batch's whole grid of tiles); the batch autotuner tries both. */
+/* Fused diagnostics of an FP32 batch (as mts_set_fused_diagnostics, with
+ * 8 rows): the diagnostic steps compute every box's windings and Gauss
+ * residual in the batched update launch, and the fix-up, cells, overlap and
+ * reduction of all boxes run as one launch each.  On by default for FP32
+ * batches with diagnostics when every box has room for its second momentum
+ * copy; rows = 0 runs the post-step kernels box by box.  Synchronises. */
+int mts_batch_set_fused_diagnostics(mts_batch *b, int32_t rows);
+int mts_batch_get_fused_diagnostics(const mts_batch *b, int32_t *rows);
+
 int mts_batch_set_tile_order(mts_batch *b, int32_t xcd_runs);
 int mts_batch_get_tile_order(const mts_batch *b, int32_t *xcd_runs);
 

@@ -1273,6 +1273,9 @@ struct mts_batch {
     void *boxes_diag_dev = nullptr;  // BatchBox<T>[nbox] for diagnostic steps (their own tile rows)
     int32_t ty_diag = 8;
     uint32_t nblk_diag = 0;
+    bool fused = false;              // FP32 diagnostic steps fused (windings, Gauss) with batched post-step launches
+    void *post_dev = nullptr;        // BatchPost<T>[nbox]
+    uint32_t nfix = 0, ncells = 0, nov = 0;   // blocks of the batched post-step launches
     bool nt = true;                  // streaming stores in the tiled update
     bool mpp = false;                // plain tiled steps write the momenta to the other copy
     bool xcd = true;                 // tiles dealt to the XCDs in contiguous runs (else round-robin)
@@ -1309,11 +1312,13 @@ template <typename T>
 int batch_upload_boxes(mts_batch *b) {
     const size_t nbox = b->box.size();
     std::vector<BatchBox<T>> h(nbox), hd(nbox);
-    uint32_t blk = 0, blkd = 0;
+    std::vector<BatchPost<T>> hp(nbox);
+    uint32_t blk = 0, blkd = 0, bfix = 0, bcells = 0, bov = 0;
     for (size_t k = 0; k < nbox; k++) {
         mts_ctx *c = b->box[k];
         c->tile = TileShape{b->ty, b->tz[k]};
-        b->ty_diag = diag_tile(c).ty;
+        c->fuse_ty = b->fused ? 8 : 0;   // the batch's fused diagnostic tile has 8 rows
+        b->ty_diag = b->fused ? 8 : diag_tile(c).ty;
         for (int pass = 0; pass < 2; pass++) {
             BatchBox<T> &x = pass == 0 ? h[k] : hd[k];
             const int ty = pass == 0 ? b->ty : b->ty_diag;
@@ -1325,6 +1330,7 @@ int batch_upload_boxes(mts_batch *b) {
             x.mom[1] = moms_at<T>(c, c->mom2 ? 1 : 0);
             x.part = Partials{c->partials, c->maxblk};
             x.alpha = static_cast<T *>(c->alpha);
+            x.wabs = c->wabs;
             x.plane = (uint32_t)c->plane;
             x.tz = b->tz[k];
             x.ntx = (c->g.nx + 63) / 64;
@@ -1335,11 +1341,35 @@ int batch_upload_boxes(mts_batch *b) {
         }
         hipError_t e = upload_nblk(c);
         if (e != hipSuccess) return bfail(b, MTS_EHIP, std::string("upload_nblk: ") + hipGetErrorString(e));
+        BatchPost<T> &q = hp[k];
+        q.g = c->g;
+        q.f[0] = fields_of<T>(c, 0);
+        q.f[1] = fields_of<T>(c, 1);
+        q.part = Partials{c->partials, c->maxblk};
+        q.wabs = c->wabs;
+        q.cells = c->cells;
+        q.bits = overlap_uses_bits(c->g) ? c->bits : nullptr;
+        q.plane = (uint32_t)c->plane;
+        q.nwords = overlap_words(c->g);
+        q.radius = c->p.overlap_radius;
+        q.h = (T)c->p.dx;
+        q.nblk = c->nblk_dev + NSLOT;
+        q.ring = c->ring;
+        q.blk_fix = bfix;
+        q.blk_cells = bcells;
+        q.blk_ov = bov;
+        bfix += wind_fix_blocks(c->g);
+        bcells += cells_blocks(c->g);
+        bov += overlap_blocks(c->g);
     }
     b->nblk = blk;
     b->nblk_diag = blkd;
+    b->nfix = bfix;
+    b->ncells = bcells;
+    b->nov = bov;
     BHIPCHK(b, hipMemcpy(b->boxes_dev, h.data(), sizeof(BatchBox<T>) * nbox, hipMemcpyHostToDevice));
     BHIPCHK(b, hipMemcpy(b->boxes_diag_dev, hd.data(), sizeof(BatchBox<T>) * nbox, hipMemcpyHostToDevice));
+    BHIPCHK(b, hipMemcpy(b->post_dev, hp.data(), sizeof(BatchPost<T>) * nbox, hipMemcpyHostToDevice));
     return MTS_OK;
 }
 
@@ -1442,19 +1472,33 @@ int batch_step_t(mts_batch *b, int32_t n, const double *eta0, const double *era_
                                      tab[(size_t)j * nbox + k], true, Partials{c->partials, c->maxblk}, b->stream);
             }
         } else {
-            // momenta to the other copy on plain steps under ping-pong, in place otherwise
-            const int mpin = c0->mcur, mpout = b->mpp && !diag ? 1 - mpin : mpin;
+            // momenta to the other copy on plain steps under ping-pong and on fused diagnostic steps, in
+            // place otherwise
+            const bool fused = diag && b->fused;
+            const int mpin = c0->mcur, mpout = (b->mpp && !diag) || fused ? 1 - mpin : mpin;
             err = launch_step_tile_batch<T>(static_cast<const BatchBox<T> *>(diag ? b->boxes_diag_dev : b->boxes_dev),
                                             (int)nbox, diag ? b->nblk_diag : b->nblk, c0->cur, mpin, mpout,
                                             static_cast<const StepCoef<T> *>(b->coef_dev) + (size_t)j * nbox, diag,
-                                            diag ? b->ty_diag : b->ty, b->nt, b->xcd, b->stream);
+                                            diag ? b->ty_diag : b->ty, b->nt, b->xcd, fused, b->stream);
             if (mpout != mpin)
                 for (mts_ctx *c : b->box) c->mcur = mpout;
         }
-        if (diag)
+        if (diag && b->fused && err == hipSuccess) {
+            // the post-step kernels of all boxes, one launch each; every box's ring advances together
+            err = launch_post_batch<T>(static_cast<const BatchPost<T> *>(b->post_dev), (int)nbox, b->nfix, b->ncells,
+                                       b->nov, c0->cur, (uint32_t)(c0->produced % RING_CAP), b->stream);
+            for (size_t k = 0; k < nbox && err == hipSuccess; k++) {
+                mts_ctx *c = b->box[k];
+                c->meta.push_back({c->step_count, eta0[k] + j * c->p.dt, books[k][j].a, svals[k][j]});
+                c->produced++;
+                c->have_cells = true;
+                c->cells_step = c->step_count;
+            }
+        } else if (diag) {
             for (size_t k = 0; k < nbox && err == hipSuccess; k++)
                 err = enqueue_diag_post<T>(b->box[k], books[k][j], eta0[k] + j * b->box[k]->p.dt, svals[k][j],
                                            b->stream, !diag_per_site(b->box[k]));
+        }
         for (mts_ctx *c : b->box) {
             c->cur = 1 - c->cur;
             c->step_count++;
@@ -1533,10 +1577,18 @@ int mts_batch_create(const mts_params *boxes, int32_t nbox, void *dev_pool, size
         if (rc == MTS_OK && e == hipSuccess) e = hipEventCreate(ev);
     if (rc == MTS_OK && e == hipSuccess) {
         const size_t bb = (b->precision == MTS_FP64 ? sizeof(BatchBox<double>) : sizeof(BatchBox<float>)) * nbox;
+        const size_t bp = (b->precision == MTS_FP64 ? sizeof(BatchPost<double>) : sizeof(BatchPost<float>)) * nbox;
         e = hipMalloc(&b->boxes_dev, bb);
         if (e == hipSuccess) e = hipMalloc(&b->boxes_diag_dev, bb);
+        if (e == hipSuccess) e = hipMalloc(&b->post_dev, bp);
     }
     if (rc == MTS_OK && e != hipSuccess) rc = MTS_ENOMEM;
+    // FP32 ensembles with diagnostics fuse them when every box has room for a second momentum copy
+    if (rc == MTS_OK && b->precision == MTS_FP32 && boxes[0].diag_every > 0) {
+        bool room = true;
+        for (mts_ctx *c : b->box) room = room && ensure_mom2_quiet(c) == MTS_OK;
+        b->fused = room;
+    }
     if (rc == MTS_OK) rc = batch_upload(b);
     if (rc != MTS_OK) {
         std::fprintf(stderr, "mts_batch_create: %s\n", b->err.c_str());
@@ -1554,6 +1606,7 @@ int mts_batch_destroy(mts_batch *b) {
     for (mts_ctx *c : b->box) mts_destroy(c);
     (void)hipFree(b->boxes_dev);
     (void)hipFree(b->boxes_diag_dev);
+    (void)hipFree(b->post_dev);
     (void)hipFree(b->coef_dev);
     for (hipEvent_t ev : {b->ev_in, b->ev_out, b->ev_t0, b->ev_t1})
         if (ev) (void)hipEventDestroy(ev);
@@ -1644,6 +1697,28 @@ int mts_batch_set_momentum_pingpong(mts_batch *b, int32_t on) {
         if (rc != MTS_OK) return rc;
     }
     b->mpp = on != 0;
+    return MTS_OK;
+}
+
+int mts_batch_set_fused_diagnostics(mts_batch *b, int32_t rows) {
+    if (!b) return MTS_EINVAL;
+    if (rows != 0 && rows != 8) return bfail(b, MTS_EINVAL, "fused diagnostics of a batch: rows must be 0 or 8");
+    if (rows && b->precision != MTS_FP32) return bfail(b, MTS_EINVAL, "fused diagnostics are FP32 only");
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->user));
+    if (rows) {
+        for (size_t k = 0; k < b->box.size(); k++) {
+            const int rc = ensure_mom2(b->box[k], "fused diagnostics");
+            if (rc != MTS_OK) return bfail(b, rc, "box " + std::to_string(k) + ": " + b->box[k]->err);
+        }
+    }
+    b->fused = rows != 0;
+    return batch_upload(b);
+}
+
+int mts_batch_get_fused_diagnostics(const mts_batch *b, int32_t *rows) {
+    if (!b || !rows) return MTS_EINVAL;
+    *rows = b->fused ? 8 : 0;
     return MTS_OK;
 }
 
@@ -1762,7 +1837,7 @@ int mts_batch_autotune(mts_batch *b, int32_t steps, int32_t *ty_out, int32_t *tz
     if ((rc = mts_batch_set_tile(b, pick_ty, tzv.data())) != MTS_OK) return rc;
     if ((rc = mts_batch_init_fields(b, seeds.data())) != MTS_OK) return rc;   // momenta back in copy 0
     if ((rc = mts_batch_set_momentum_pingpong(b, pick_mpp ? 1 : 0)) != MTS_OK) return rc;
-    if (!pick_mpp) {                                  // the second momentum copies are not needed
+    if (!pick_mpp && !b->fused) {                     // the second momentum copies are not needed
         BHIPCHK(b, hipStreamSynchronize(b->stream));
         for (mts_ctx *c : b->box) {
             (void)hipFree(c->mom2);

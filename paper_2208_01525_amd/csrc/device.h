@@ -205,6 +205,23 @@ __device__ __forceinline__ T link_chi_exact(cx<T> a, cx<T> b, T hA) {
     return z0 ? T(0) : (T)exact_link_phase(a.re, a.im, b.re, b.im, (double)hA);
 }
 
+// Wrap count of a link for the fused windings: with v = (ab - aa) - h A,
+// n = rint(v / 2 pi) and chi = v - 2 pi n.  Around a plaquette the phase
+// differences telescope and the h A terms make up the plaquette angle, so the
+// winding through a face is minus the oriented sum of its four links' wrap
+// counts.  `flag` where the guard asks for FP64 instead (|chi| within
+// Guard::cut of the branch cut, |h A| above Guard::big, or a NaN phase at a
+// zero of the field); an unflagged count has |n| < 256.
+template <typename T>
+__device__ __forceinline__ int link_wrap(T aa, T ab, T hA, bool &flag) {
+#pragma clang fp contract(off)
+    const T v = (ab - aa) - hA;
+    const T n = rint_t(v * (T(0.5) / Pi<T>::v));
+    const T chi = v - (T(2) * Pi<T>::v) * n;
+    flag = !(fabs(chi) <= Pi<T>::v - Guard<T>::cut && fabs(hA) <= Guard<T>::big);
+    return flag ? 0 : (int)n;
+}
+
 // chi + h A of a link for the fused diagnostics, or NaN where the guard asks
 // for the FP64 product (near the branch cut or |h A| above Guard::big; a NaN
 // phase, phi = 0 at an end, gives NaN by itself).

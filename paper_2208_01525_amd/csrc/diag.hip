@@ -198,10 +198,10 @@ uint32_t wind_fix_blocks(const Geom &g) {
 // for it).  A thread scans 16 sites per sector with one 16-byte load (the
 // sector's byte plane is padded to a multiple of 64 sites).
 template <typename T>
-__global__ __launch_bounds__(256) void wind_fix_kernel(Geom g, Fields<T> f, T h, uint8_t *wabs, uint32_t plane,
-                                                       Partials part) {
+__device__ __forceinline__ void fix_block(const Geom &g, const Fields<T> &f, T h, uint8_t *wabs, uint32_t plane,
+                                          Partials part, uint32_t lblk, uint32_t tid) {
     const uint32_t S = g.nxy * (uint32_t)g.nz;
-    const uint32_t s0 = (blockIdx.x * 256 + threadIdx.x) * FIX_SITES;
+    const uint32_t s0 = (lblk * 256 + tid) * FIX_SITES;
     double acc[2] = {0, 0};
     if (s0 < S) {
 #pragma unroll
@@ -231,7 +231,13 @@ __global__ __launch_bounds__(256) void wind_fix_kernel(Geom g, Fields<T> f, T h,
             }
         }
     }
-    block_sum_store<2, 4>(acc, part, SL_FIX_P, blockIdx.x);
+    block_sum_store<2, 4>(acc, part, SL_FIX_P, lblk);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void wind_fix_kernel(Geom g, Fields<T> f, T h, uint8_t *wabs, uint32_t plane,
+                                                       Partials part) {
+    fix_block(g, f, h, wabs, plane, part, blockIdx.x, threadIdx.x);
 }
 
 template <typename T>
@@ -264,13 +270,12 @@ uint32_t overlap_words(const Geom &g) { return (uint32_t)(g.nx / 64) * (uint32_t
 // less.
 constexpr int CZ = 16;
 
-__global__ __launch_bounds__(256) void cells_kernel(Geom g, const uint8_t *wabs, uint8_t *cells, uint64_t *bits,
-                                                    uint32_t plane, uint32_t nwords) {
+__device__ __forceinline__ void cells_block(const Geom &g, const uint8_t *wabs, uint8_t *cells, uint64_t *bits,
+                                            uint32_t plane, uint32_t nwords, uint32_t blk, int tx, int ty) {
     const uint32_t gx = (g.nx + 63) / 64, gy = (g.ny + 3) / 4;
-    const uint32_t blk = xcd_order(blockIdx.x, gridDim.x);
     const uint32_t bx = blk % gx, by = (blk / gx) % gy, bz = blk / (gx * gy);
-    const int x = bx * 64 + threadIdx.x;
-    const int y = by * 4 + threadIdx.y;
+    const int x = bx * 64 + tx;
+    const int y = by * 4 + ty;
     const bool in = x < g.nx && y < g.ny;
     const int z0 = bz * CZ, z1 = min(z0 + CZ, g.nz);
     const uint32_t col = in ? (uint32_t)x + (uint32_t)g.nx * (uint32_t)y : 0u;
@@ -297,7 +302,7 @@ __global__ __launch_bounds__(256) void cells_kernel(Geom g, const uint8_t *wabs,
         }
         if (bits) {   // nx % 64 == 0: the wave is one 64-cell word of one row
             const uint64_t mp = __ballot(in && n[0] > 0), mq = __ballot(in && n[1] > 0);
-            if (threadIdx.x == 0 && in) {
+            if (tx == 0 && in) {
                 const uint32_t wi = (uint32_t)(x / 64) + (uint32_t)(g.nx / 64) * ((uint32_t)y + (uint32_t)g.ny * z);
                 bits[wi] = mp;
                 bits[(size_t)nwords + wi] = mq;
@@ -306,11 +311,15 @@ __global__ __launch_bounds__(256) void cells_kernel(Geom g, const uint8_t *wabs,
     }
 }
 
+__global__ __launch_bounds__(256) void cells_kernel(Geom g, const uint8_t *wabs, uint8_t *cells, uint64_t *bits,
+                                                    uint32_t plane, uint32_t nwords) {
+    cells_block(g, wabs, cells, bits, plane, nwords, xcd_order(blockIdx.x, gridDim.x), threadIdx.x, threadIdx.y);
+}
+
 hipError_t launch_cells(const Geom &g, const uint8_t *wabs, uint8_t *cells, uint64_t *bits, uint32_t plane,
                         hipStream_t st) {
     dim3 block(64, 4, 1);
-    dim3 grid((unsigned)((g.nx + 63) / 64) * (unsigned)((g.ny + 3) / 4) * (unsigned)((g.nz + CZ - 1) / CZ), 1, 1);
-    cells_kernel<<<grid, block, 0, st>>>(g, wabs, cells, overlap_uses_bits(g) ? bits : nullptr, plane,
+    cells_kernel<<<cells_blocks(g), block, 0, st>>>(g, wabs, cells, overlap_uses_bits(g) ? bits : nullptr, plane,
                                          overlap_words(g));
     return hipGetLastError();
 }
@@ -329,9 +338,9 @@ __device__ __forceinline__ uint64_t dilate_x(const uint64_t *m, uint32_t row, in
     return w | (w << 1) | (w >> 1) | (l >> 63) | (r << 63);
 }
 
-__global__ __launch_bounds__(256) void overlap_bits_kernel(Geom g, const uint64_t *bits, uint32_t nwords, int radius,
-                                                           Partials part) {
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void overlap_bits_block(const Geom &g, const uint64_t *bits, uint32_t nwords, int radius,
+                                                   Partials part, uint32_t lblk, uint32_t tid) {
+    const uint32_t i = lblk * 256 + tid;
     double acc[2] = {0, 0};
     if (i < nwords) {
         const int nw = g.nx / 64;
@@ -353,14 +362,16 @@ __global__ __launch_bounds__(256) void overlap_bits_kernel(Geom g, const uint64_
             acc[sec] = (double)__popcll(own[i] & d);
         }
     }
-    block_sum_store<2, 4>(acc, part, SL_OV_P, blockIdx.x);
+    block_sum_store<2, 4>(acc, part, SL_OV_P, lblk);
 }
 
-__global__ __launch_bounds__(256) void overlap_bytes_kernel(Geom g, const uint8_t *cells, uint32_t plane, int radius,
-                                                            Partials part) {
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
-    const int z = blockIdx.z;
+// lblk = bx + gx (by + gy z): 64 x 4 columns of one plane
+__device__ __forceinline__ void overlap_bytes_block(const Geom &g, const uint8_t *cells, uint32_t plane, int radius,
+                                                    Partials part, uint32_t lblk, int tx, int ty) {
+    const uint32_t gx = (g.nx + 63) / 64, gy = (g.ny + 3) / 4;
+    const int x = (lblk % gx) * 64 + tx;
+    const int y = ((lblk / gx) % gy) * 4 + ty;
+    const int z = lblk / (gx * gy);
     double acc[2] = {0, 0};
     if (x < g.nx && y < g.ny) {
         const uint32_t s = x + g.nx * y + g.nxy * z;
@@ -382,8 +393,17 @@ __global__ __launch_bounds__(256) void overlap_bytes_kernel(Geom g, const uint8_
             acc[sec] = hit ? 1.0 : 0.0;
         }
     }
-    const uint32_t blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-    block_sum_store<2, 4>(acc, part, SL_OV_P, blk);
+    block_sum_store<2, 4>(acc, part, SL_OV_P, lblk);
+}
+
+__global__ __launch_bounds__(256) void overlap_bits_kernel(Geom g, const uint64_t *bits, uint32_t nwords, int radius,
+                                                           Partials part) {
+    overlap_bits_block(g, bits, nwords, radius, part, blockIdx.x, threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void overlap_bytes_kernel(Geom g, const uint8_t *cells, uint32_t plane, int radius,
+                                                            Partials part) {
+    overlap_bytes_block(g, cells, plane, radius, part, blockIdx.x, threadIdx.x & 63, threadIdx.x >> 6);
 }
 
 hipError_t launch_overlap(const Geom &g, const uint8_t *cells, const uint64_t *bits, uint32_t plane, int radius,
@@ -392,9 +412,7 @@ hipError_t launch_overlap(const Geom &g, const uint8_t *cells, const uint64_t *b
         const uint32_t nw = overlap_words(g);
         overlap_bits_kernel<<<(nw + 255) / 256, 256, 0, st>>>(g, bits, nw, radius, part);
     } else {
-        dim3 block(64, 4, 1);
-        dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
-        overlap_bytes_kernel<<<grid, block, 0, st>>>(g, cells, plane, radius, part);
+        overlap_bytes_kernel<<<overlap_blocks(g), 256, 0, st>>>(g, cells, plane, radius, part);
     }
     return hipGetLastError();
 }
@@ -403,9 +421,8 @@ hipError_t launch_overlap(const Geom &g, const uint8_t *cells, const uint64_t *b
 
 // One block per slot; thread t sums partials t, t + 1024, ... in order (four
 // independent running sums combined in a fixed order), then a fixed tree.
-__global__ __launch_bounds__(1024) void reduce_kernel(Partials part, const uint32_t *nblk, double *rec) {
+__device__ __forceinline__ void reduce_block(Partials part, const uint32_t *nblk, double *rec, int slot) {
     __shared__ double red[1024];
-    const int slot = blockIdx.x;
     const uint32_t n = nblk[slot];
     const double *p = part.base + (size_t)slot * part.maxblk;
     double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
@@ -426,10 +443,99 @@ __global__ __launch_bounds__(1024) void reduce_kernel(Partials part, const uint3
     if (threadIdx.x == 0) rec[slot] = red[0];
 }
 
+__global__ __launch_bounds__(1024) void reduce_kernel(Partials part, const uint32_t *nblk, double *rec) {
+    reduce_block(part, nblk, rec, blockIdx.x);
+}
+
 hipError_t launch_reduce(Partials part, const uint32_t *nblk_per_slot_dev, double *rec, hipStream_t st) {
     reduce_kernel<<<NSLOT, 1024, 0, st>>>(part, nblk_per_slot_dev, rec);
     return hipGetLastError();
 }
+
+// ---------------------------------------------------------------- ensembles
+
+// the last box whose first block (member `first`) is <= t
+template <typename B>
+__device__ __forceinline__ int box_of(const B *boxes, int nbox, uint32_t t, uint32_t B::*first) {
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (boxes[mid].*first <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T>
+__device__ __forceinline__ Fields<T> fields_global(const Fields<T> &f) {
+    Fields<T> r;
+#pragma unroll
+    for (int sec = 0; sec < 2; sec++) {
+        r.phi[sec] = as_global(f.phi[sec]);
+#pragma unroll
+        for (int i = 0; i < 3; i++) r.A[sec][i] = as_global(f.A[sec][i]);
+    }
+    return r;
+}
+
+__device__ __forceinline__ Partials part_global(Partials p) {
+    p.base = as_global(p.base);
+    return p;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void fix_batch_kernel(const BatchPost<T> *boxes, int nbox, int parity) {
+    const int k = box_of(boxes, nbox, blockIdx.x, &BatchPost<T>::blk_fix);
+    const BatchPost<T> &b = boxes[k];
+    fix_block(b.g, fields_global(b.f[parity]), b.h, as_global(b.wabs), b.plane, part_global(b.part),
+              blockIdx.x - b.blk_fix, threadIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void cells_batch_kernel(const BatchPost<T> *boxes, int nbox, uint32_t total) {
+    const uint32_t t = xcd_order(blockIdx.x, total);
+    const int k = box_of(boxes, nbox, t, &BatchPost<T>::blk_cells);
+    const BatchPost<T> &b = boxes[k];
+    cells_block(b.g, as_global(b.wabs), as_global(b.cells), b.bits ? as_global(b.bits) : nullptr, b.plane, b.nwords,
+                t - b.blk_cells, threadIdx.x & 63, threadIdx.x >> 6);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void overlap_batch_kernel(const BatchPost<T> *boxes, int nbox) {
+    const int k = box_of(boxes, nbox, blockIdx.x, &BatchPost<T>::blk_ov);
+    const BatchPost<T> &b = boxes[k];
+    const uint32_t l = blockIdx.x - b.blk_ov;
+    if (b.bits)
+        overlap_bits_block(b.g, as_global(b.bits), b.nwords, b.radius, part_global(b.part), l, threadIdx.x);
+    else
+        overlap_bytes_block(b.g, as_global(b.cells), b.plane, b.radius, part_global(b.part), l, threadIdx.x & 63,
+                            threadIdx.x >> 6);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void reduce_batch_kernel(const BatchPost<T> *boxes, uint32_t ring_idx) {
+    const BatchPost<T> &b = boxes[blockIdx.y];
+    reduce_block(part_global(b.part), as_global(b.nblk), as_global(b.ring) + (size_t)ring_idx * NSLOT, blockIdx.x);
+}
+
+uint32_t cells_blocks(const Geom &g) {
+    return (uint32_t)((g.nx + 63) / 64) * (uint32_t)((g.ny + 3) / 4) * (uint32_t)((g.nz + CZ - 1) / CZ);
+}
+
+template <typename T>
+hipError_t launch_post_batch(const BatchPost<T> *boxes_dev, int nbox, uint32_t nfix, uint32_t ncells, uint32_t nov,
+                             int parity, uint32_t ring_idx, hipStream_t st) {
+    fix_batch_kernel<T><<<nfix, 256, 0, st>>>(boxes_dev, nbox, parity);
+    cells_batch_kernel<T><<<ncells, 256, 0, st>>>(boxes_dev, nbox, ncells);
+    overlap_batch_kernel<T><<<nov, 256, 0, st>>>(boxes_dev, nbox);
+    reduce_batch_kernel<T><<<dim3(NSLOT, (unsigned)nbox, 1), 1024, 0, st>>>(boxes_dev, ring_idx);
+    return hipGetLastError();
+}
+
+template hipError_t launch_post_batch<float>(const BatchPost<float> *, int, uint32_t, uint32_t, uint32_t, int,
+                                             uint32_t, hipStream_t);
+template hipError_t launch_post_batch<double>(const BatchPost<double> *, int, uint32_t, uint32_t, uint32_t, int,
+                                              uint32_t, hipStream_t);
 
 template hipError_t launch_phase<float>(const Geom &, Fields<float>, float *, uint32_t, hipStream_t);
 template hipError_t launch_phase<double>(const Geom &, Fields<double>, double *, uint32_t, hipStream_t);

@@ -145,16 +145,42 @@ struct BatchBox {
     Moms<T> mom[2];       // momentum copies 0 and 1 (both the state buffer's without a second copy)
     Partials part;        // this box's partials (box-local block index)
     T *alpha;             // this box's phase scratch [2][plane]
+    uint8_t *wabs;        // this box's packed |W| bytes (fused diagnostic steps)
     uint32_t plane;
     int32_t ntx, nty, ntz, tz;
     uint32_t blk0;        // first block of this box in the launch
 };
 // Fields from copy `parity` to the other; momenta from copy `mpin` to copy
-// `mpout` (equal: in place).
+// `mpout` (equal: in place).  With diag and fused (FP32, ty 8, mpout != mpin)
+// the windings and the Gauss residual are computed in the same pass, as
+// launch_step_tile does with wabs.
 template <typename T>
 hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32_t nblk, int parity, int mpin,
                                   int mpout, const StepCoef<T> *coef_dev, bool diag, int ty, bool nt, bool xcd,
-                                  hipStream_t st);
+                                  bool fused, hipStream_t st);
+
+// One box of an ensemble in the batched post-step launches of a fused
+// diagnostic step: the fix-up of the windings, the cells, the overlap and the
+// reduction each run as one launch over all boxes.
+template <typename T>
+struct BatchPost {
+    Geom g;
+    Fields<T> f[2];       // field copies 0 and 1 (the step's input copy is `parity`)
+    Partials part;
+    uint8_t *wabs, *cells;
+    uint64_t *bits;       // occupancy words (nx % 64 == 0); null: the byte overlap
+    uint32_t plane, nwords;
+    int32_t radius;
+    T h;
+    const uint32_t *nblk; // the box's partial counts per slot (fused path)
+    double *ring;         // the box's record ring [RING_CAP][NSLOT]
+    uint32_t blk_fix, blk_cells, blk_ov;   // the box's first block in each batched launch
+};
+uint32_t cells_blocks(const Geom &g);
+// Records go to ring + ring_idx * NSLOT of every box.
+template <typename T>
+hipError_t launch_post_batch(const BatchPost<T> *boxes_dev, int nbox, uint32_t nfix, uint32_t ncells, uint32_t nov,
+                             int parity, uint32_t ring_idx, hipStream_t st);
 
 // Phase alpha = arg(phi) of every site and sector into alpha[2][plane]
 // (NaN where phi = 0), input of the winding kernel.

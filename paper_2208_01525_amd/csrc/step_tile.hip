@@ -36,10 +36,10 @@ __device__ __forceinline__ int wrapi(int v, int n) {
 }
 
 // LDS quantities per sector; the fused diagnostic variant adds the phase of
-// the next plane, the link values c = chi + h A of the plane and the new
-// electric fields E_x, E_y (for the divergence at x + i)
+// the next plane and the new electric fields E_x, E_y (for the divergence at
+// x + i)
 enum Q { Q_FR, Q_FI, Q_UXR, Q_UXI, Q_UYR, Q_UYI, Q_UZR, Q_UZI, Q_SXY, Q_SXZ, Q_SYZ, NQ };
-enum QF { Q_AN = NQ, Q_CX, Q_CY, Q_CZ, Q_EX, Q_EY, NQF };
+enum QF { Q_AN = NQ, Q_EX, Q_EY, NQF };
 
 template <typename T, int TY, int NQX = NQ>
 struct Lds {
@@ -61,7 +61,23 @@ struct FusedLds {
     int wsum[2][64 * TY];     // sum |W| p, q
     T ez[2][64 * TY];
     T gr[2][64 * TY];
+    int nw[2][(TY + 2) * LW]; // the plane's packed link wrap counts, every site of the tile
 };
+
+// Packed wrap counts of a site's three links (x, y, z: 9-bit fields, two's
+// complement) and their guard flags (bits 27, 28, 29).
+__device__ __forceinline__ int wrap_word(int nx, int ny, int nz, bool fx, bool fy, bool fz) {
+    return (nx & 0x1FF) | ((ny & 0x1FF) << 9) | ((nz & 0x1FF) << 18) | ((int)fx << 27) | ((int)fy << 28) |
+           ((int)fz << 29);
+}
+template <int K>
+__device__ __forceinline__ int wrap_n(int w) {
+    return (int)((uint32_t)w << (23 - 9 * K)) >> 23;
+}
+template <int K>
+__device__ __forceinline__ int wrap_f(int w) {
+    return (w >> (27 + K)) & 1;
+}
 template <typename T, int TY>
 struct NoFusedLds {};
 
@@ -94,12 +110,14 @@ constexpr int NACC_FUSED = SL_WIND_Q + 1;
 // FUSE (with DIAG): the windings and the Gauss residual of the step's input
 // fields are computed here as well, and no phase is stored.  Per plane z,
 // every thread stages the phase alpha(z+1) of its site; then it forms the
-// link values c_mu = chi_mu + h A_mu of its links at z (c_z) and z+1 (c_x,
-// c_y, carried to the next plane), stages those of z, and the interior
+// wrap counts n_mu of its links at z (n_z) and z+1 (n_x, n_y, carried to the
+// next plane), stages those of z packed in one word, and the interior
 // threads take the windings through the three faces at their site,
-//   W_z = rint[(c_x(x) + c_y(x+x) - c_x(x+y) - c_y(x)) / 2 pi]  (and cyclic),
-// with the guard of link_chi, so they equal the post-step kernel's bit for
-// bit.  The Gauss residual C = div E^{n+1/2} - g Im[conj(phi^n) Pi^{n+1/2}]
+//   W_z = -(n_x(x) + n_y(x+x) - n_x(x+y) - n_y(x))  (and cyclic),
+// the value rint of the post-step kernel's sum of link phases and plaquette
+// angle takes when no link of the face is flagged by the guard; a face with
+// a flagged link marks its site for the fix-up kernel.
+// The Gauss residual C = div E^{n+1/2} - g Im[conj(phi^n) Pi^{n+1/2}]
 // needs the new E at x - i: the interior threads stage their E_x, E_y; the
 // halo column x0 - 1 and row y0 - 1 recompute theirs (E_x and E_y only, with
 // the same arithmetic as their owning tile), and at the plane below the tile
@@ -160,8 +178,9 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
     T cA[2][3], nA[2][3];
     cx<T> cU[2][3], nU[2][3], pUz[2];
     T psxz[2], psyz[2];
-    // fused: alpha(z); c_x(z), c_y(z); E_z^{n+1/2}(z-1)
-    T alc[2], cxc[2], cyc[2], ezp[2];
+    // fused: alpha(z); packed wrap counts of the x and y links at z; E_z^{n+1/2}(z-1)
+    T alc[2], ezp[2];
+    int wxy[2];
     const int it = w * 64 + lx;            // interior thread's slot in FL
     auto load_raw = [&](int zz, cx<T> (&f)[2], T (&A)[2][3]) {
         const uint32_t s = colidx + g.nxy * (uint32_t)zz;
@@ -198,8 +217,7 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
 #pragma unroll
         for (int sec = 0; sec < 2; sec++) {
             alc[sec] = phase_of(cf[sec]);
-            cxc[sec] = T(0);
-            cyc[sec] = T(0);
+            wxy[sec] = 0;
             ezp[sec] = T(0);
         }
         if (interior) {
@@ -265,8 +283,15 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
             }
         }
 
-        // stage phi and U of plane z (fused: and the phase of plane z+1)
+        // stage phi and U of plane z (fused: and the phase of plane z+1; the
+        // phase of plane z is the one this thread staged one plane before)
         T aln[2] = {T(0), T(0)};
+        if constexpr (FUSE) {
+            if (owner && z > zbeg - 1) {
+#pragma unroll
+                for (int sec = 0; sec < 2; sec++) alc[sec] = L.v[sec][Q_AN][li];
+            }
+        }
         if (owner) {
 #pragma unroll
             for (int sec = 0; sec < 2; sec++) {
@@ -298,24 +323,20 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                 L.v[sec][Q_SYZ][li] = sn[sec][2];
             }
         }
-        // fused: link values c of plane z+1 (x and y links, where the
-        // neighbour lies in the tile) and of plane z (z link); stage those of z
-        T cxn[2], cyn[2], czc[2];
+        // fused: wrap counts of the x and y links of plane z+1 and of the z
+        // link of plane z (garbage where the neighbour lies outside the tile:
+        // no face reads those); stage the word of plane z
+        int wnext[2], wown[2];
         if constexpr (FUSE) {
-            // a link the guard flags (near the branch cut, at a zero of the
-            // field, or a large angle) gets the value NaN: every face it
-            // bounds then sums to NaN and its site is left to the fix-up
-            // kernel, which takes the FP64 product there
 #pragma unroll
             for (int sec = 0; sec < 2; sec++) {
-                cxn[sec] = link_value_or_nan(aln[sec], L.v[sec][Q_AN][lxp], link_angle(c.h, nA[sec][0]));
-                cyn[sec] = link_value_or_nan(aln[sec], L.v[sec][Q_AN][lyp], link_angle(c.h, nA[sec][1]));
-                czc[sec] = link_value_or_nan(alc[sec], aln[sec], link_angle(c.h, cA[sec][2]));
-                if (owner) {
-                    L.v[sec][Q_CX][li] = cxc[sec];
-                    L.v[sec][Q_CY][li] = cyc[sec];
-                    L.v[sec][Q_CZ][li] = czc[sec];
-                }
+                bool fx, fy, fz;
+                const int nx_ = link_wrap(aln[sec], L.v[sec][Q_AN][lxp], link_angle(c.h, nA[sec][0]), fx);
+                const int ny_ = link_wrap(aln[sec], L.v[sec][Q_AN][lyp], link_angle(c.h, nA[sec][1]), fy);
+                const int nz_ = link_wrap(alc[sec], aln[sec], link_angle(c.h, cA[sec][2]), fz);
+                wnext[sec] = wrap_word(nx_, ny_, 0, fx, fy, false);
+                wown[sec] = wxy[sec] | wrap_word(0, 0, nz_, false, false, fz);
+                if (owner) FL.nw[sec][li] = wown[sec];
             }
         }
         __syncthreads();
@@ -323,15 +344,17 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
         if constexpr (FUSE) {
             if (upd) {
                 // windings through the three faces at the site (lower corner x)
-                const T inv2pi = T(0.5) / Pi<T>::v;
 #pragma unroll
                 for (int sec = 0; sec < 2; sec++) {
-                    const T sz = (((cxc[sec] + L.v[sec][Q_CY][lxp]) - L.v[sec][Q_CX][lyp]) - cyc[sec]) * inv2pi;
-                    const T sx = (((cyc[sec] + L.v[sec][Q_CZ][lyp]) - cyn[sec]) - czc[sec]) * inv2pi;
-                    const T sy = (((czc[sec] + cxn[sec]) - L.v[sec][Q_CZ][lxp]) - cxc[sec]) * inv2pi;
+                    const int o = wown[sec], xp = FL.nw[sec][lxp], yp = FL.nw[sec][lyp], zp = wnext[sec];
+                    const int Wz = -(((wrap_n<0>(o) + wrap_n<1>(xp)) - wrap_n<0>(yp)) - wrap_n<1>(o));
+                    const int Wx = -(((wrap_n<1>(o) + wrap_n<2>(yp)) - wrap_n<1>(zp)) - wrap_n<2>(o));
+                    const int Wy = -(((wrap_n<2>(o) + wrap_n<0>(zp)) - wrap_n<2>(xp)) - wrap_n<0>(o));
+                    const int flagged = (wrap_f<0>(o) | wrap_f<1>(o) | wrap_f<2>(o)) | wrap_f<1>(xp) |
+                                        wrap_f<2>(xp) | wrap_f<0>(yp) | wrap_f<2>(yp) | wrap_f<0>(zp) | wrap_f<1>(zp);
                     uint8_t byte = WABS_FIX;
-                    if (!(isnan(sz) || isnan(sx) || isnan(sy))) {
-                        const int aWx = abs((int)rint_t(sx)), aWy = abs((int)rint_t(sy)), aWz = abs((int)rint_t(sz));
+                    if (!flagged) {
+                        const int aWx = abs(Wx), aWy = abs(Wy), aWz = abs(Wz);
                         byte = (uint8_t)(min(aWx, 3) | (min(aWy, 3) << 2) | (min(aWz, 3) << 4));
                         FL.wsum[sec][it] += aWx + aWy + aWz;
                     }
@@ -472,11 +495,7 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                 }
             }
 #pragma unroll
-            for (int sec = 0; sec < 2; sec++) {
-                alc[sec] = aln[sec];
-                cxc[sec] = cxn[sec];
-                cyc[sec] = cyn[sec];
-            }
+            for (int sec = 0; sec < 2; sec++) wxy[sec] = wnext[sec];
         }
 
         // rotate registers
@@ -520,13 +539,14 @@ __global__ __launch_bounds__(64 * (TY + 3)) void step_tile_kernel(Geom g, Fields
 
 // Ensemble of boxes in one launch: the blocks of box k are [blk0[k], blk0[k+1])
 // of the XCD-ordered grid; each box has its own fields, coefficients and
-// partials (indexed by the box-local block).
-template <typename T, bool DIAG, int TY, bool NT>
+// partials (indexed by the box-local block).  FUSE as for single boxes.
+template <typename T, bool DIAG, int TY, bool NT, bool FUSE = false>
 __global__ __launch_bounds__(64 * (TY + 3)) void step_tile_batch_kernel(const BatchBox<T> *boxes, int nbox,
                                                                         int parity, int mpin, int mpout,
                                                                         const StepCoef<T> *coef, uint32_t nblk,
                                                                         int xcd) {
-    __shared__ Lds<T, TY> L;
+    __shared__ Lds<T, TY, FUSE ? NQF : NQ> L;
+    __shared__ typename std::conditional<FUSE, FusedLds<T, TY>, NoFusedLds<T, TY>>::type FL;
     const uint32_t t = xcd ? xcd_order(blockIdx.x, nblk) : blockIdx.x;
     int lo = 0, hi = nbox - 1;             // last box with blk0 <= t
     while (lo < hi) {
@@ -554,14 +574,14 @@ __global__ __launch_bounds__(64 * (TY + 3)) void step_tile_batch_kernel(const Ba
             mom_out.E[sec][i] = as_global(bx.mom[mpout].E[sec][i]);
         }
     }
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    NoFusedLds<T, TY> nf;
-    tile_step<T, DIAG, TY, NT>(bx.g, fin, fout, mom, mom_out, coef[lo], tx * 64, ty_ * TY, tz * bx.tz, bx.tz, L, acc,
-                               as_global(bx.alpha), nullptr, bx.plane, nf);
+    double acc[FUSE ? NACC_FUSED : 6] = {};
+    tile_step<T, DIAG, TY, NT, false, 0, FUSE>(bx.g, fin, fout, mom, mom_out, coef[lo], tx * 64, ty_ * TY,
+                                               tz * bx.tz, bx.tz, L, acc, as_global(bx.alpha),
+                                               FUSE ? as_global(bx.wabs) : nullptr, bx.plane, FL);
     if constexpr (DIAG) {
         Partials part = bx.part;
         part.base = as_global(part.base);
-        block_sum_store<6, TY + 3>(acc, part, SL_EPS, lt);
+        block_sum_store<FUSE ? NACC_FUSED : 6, TY + 3>(acc, part, SL_EPS, lt);
     }
 }
 
@@ -690,11 +710,23 @@ hipError_t launch_step_tile(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> 
 template <typename T>
 hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32_t nblk, int parity, int mpin,
                                   int mpout, const StepCoef<T> *coef_dev, bool diag, int ty, bool nt, bool xcd,
-                                  hipStream_t st) {
+                                  bool fused, hipStream_t st) {
     dim3 grid(nblk, 1, 1);
-#define MTS_BATCH_LAUNCH(TYV, D, N)                                                                                 \
-    step_tile_batch_kernel<T, D, TYV, N><<<grid, dim3(64, TYV + 3, 1), 0, st>>>(boxes_dev, nbox, parity, mpin,   \
-                                                                                 mpout, coef_dev, nblk, xcd ? 1 : 0)
+#define MTS_BATCH_LAUNCH(TYV, D, N, FU)                                                                            \
+    step_tile_batch_kernel<T, D, TYV, N, FU><<<grid, dim3(64, TYV + 3, 1), 0, st>>>(boxes_dev, nbox, parity, mpin, \
+                                                                                     mpout, coef_dev, nblk,        \
+                                                                                     xcd ? 1 : 0)
+    if (diag && fused) {
+        // fused diagnostics: FP32, 8 rows, momenta out of place
+        if constexpr (sizeof(T) == 4) {
+            if (ty != 8 || mpin == mpout) return hipErrorInvalidValue;
+            if (nt) MTS_BATCH_LAUNCH(8, true, true, true);
+            else MTS_BATCH_LAUNCH(8, true, false, true);
+            return hipGetLastError();
+        } else {
+            return hipErrorNotSupported;
+        }
+    }
     // as for single boxes: no diagnostic variant for the shapes only plain steps use
 #define MTS_BATCH_CASE(TYV)                                           \
     case TYV:                                                         \
@@ -702,12 +734,12 @@ hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32
             if constexpr (TYV == 13 || (TYV == 5 && sizeof(T) == 8)) {  \
                 return hipErrorNotSupported;                          \
             } else {                                                  \
-                if (nt) MTS_BATCH_LAUNCH(TYV, true, true);            \
-                else MTS_BATCH_LAUNCH(TYV, true, false);              \
+                if (nt) MTS_BATCH_LAUNCH(TYV, true, true, false);     \
+                else MTS_BATCH_LAUNCH(TYV, true, false, false);       \
             }                                                         \
         } else {                                                      \
-            if (nt) MTS_BATCH_LAUNCH(TYV, false, true);               \
-            else MTS_BATCH_LAUNCH(TYV, false, false);                 \
+            if (nt) MTS_BATCH_LAUNCH(TYV, false, true, false);        \
+            else MTS_BATCH_LAUNCH(TYV, false, false, false);          \
         }                                                             \
         return hipGetLastError();
     switch (ty) {
@@ -718,8 +750,8 @@ hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32
         case 13:
             if constexpr (sizeof(T) == 4) {
                 if (diag) return hipErrorNotSupported;
-                if (nt) MTS_BATCH_LAUNCH(13, false, true);
-                else MTS_BATCH_LAUNCH(13, false, false);
+                if (nt) MTS_BATCH_LAUNCH(13, false, true, false);
+                else MTS_BATCH_LAUNCH(13, false, false, false);
                 return hipGetLastError();
             } else {
                 return hipErrorInvalidValue;
@@ -731,9 +763,10 @@ hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32
 }
 
 template hipError_t launch_step_tile_batch<float>(const BatchBox<float> *, int, uint32_t, int, int, int,
-                                                  const StepCoef<float> *, bool, int, bool, bool, hipStream_t);
+                                                  const StepCoef<float> *, bool, int, bool, bool, bool, hipStream_t);
 template hipError_t launch_step_tile_batch<double>(const BatchBox<double> *, int, uint32_t, int, int, int,
-                                                   const StepCoef<double> *, bool, int, bool, bool, hipStream_t);
+                                                   const StepCoef<double> *, bool, int, bool, bool, bool,
+                                                   hipStream_t);
 
 template hipError_t launch_step_tile<float>(const Geom &, Fields<float>, Fields<float>, Moms<float>, Moms<float>,
                                             const StepCoef<float> &, bool, Partials, TileShape, float *, uint8_t *,

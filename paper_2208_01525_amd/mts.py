@@ -26,7 +26,7 @@ EXPORTS = ("mts_state_bytes", "mts_create", "mts_destroy", "mts_init_fields", "m
            "mts_batch_state_bytes", "mts_batch_create", "mts_batch_destroy", "mts_batch_size",
            "mts_batch_init_fields", "mts_batch_step", "mts_batch_diagnostics", "mts_batch_get_fields",
            "mts_batch_set_fields", "mts_batch_set_tile", "mts_batch_set_streaming_stores", "mts_batch_get_streaming_stores", "mts_batch_set_momentum_pingpong",
-           "mts_batch_get_momentum_pingpong", "mts_batch_set_tile_order", "mts_batch_get_tile_order", "mts_batch_timing_read", "mts_batch_autotune",
+           "mts_batch_get_momentum_pingpong", "mts_batch_set_fused_diagnostics", "mts_batch_get_fused_diagnostics", "mts_batch_set_tile_order", "mts_batch_get_tile_order", "mts_batch_timing_read", "mts_batch_autotune",
            "mts_batch_last_error")
 
 
@@ -120,6 +120,8 @@ def load():
     L.mts_batch_get_streaming_stores.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.mts_batch_set_momentum_pingpong.argtypes = [vp, ctypes.c_int32]
     L.mts_batch_get_momentum_pingpong.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.mts_batch_set_fused_diagnostics.argtypes = [vp, ctypes.c_int32]
+    L.mts_batch_get_fused_diagnostics.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.mts_batch_set_tile_order.argtypes = [vp, ctypes.c_int32]
     L.mts_batch_get_tile_order.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.mts_get_tile.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
@@ -469,6 +471,15 @@ class Batch:
 
     def set_momentum_pingpong(self, on):
         self._check(self.L.mts_batch_set_momentum_pingpong(self.b, 1 if on else 0))
+
+    def set_fused_diagnostics(self, rows):
+        """8: fused diagnostic steps with batched post-step launches; 0: box by box."""
+        self._check(self.L.mts_batch_set_fused_diagnostics(self.b, int(rows)))
+
+    def get_fused_diagnostics(self):
+        v = ctypes.c_int32()
+        self._check(self.L.mts_batch_get_fused_diagnostics(self.b, ctypes.byref(v)))
+        return v.value
 
     def set_tile_order(self, xcd_runs):
         self._check(self.L.mts_batch_set_tile_order(self.b, 1 if xcd_runs else 0))

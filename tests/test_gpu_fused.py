@@ -150,3 +150,39 @@ def test_fused_guard_cases_match_oracle(rows):
         assert rec["wind_abs"] == (int(np.abs(W[:3]).sum()), int(np.abs(W[3:]).sum()))
         assert np.array_equal(lat.get_cells().astype(np.int32), ref_cells)
         lat.close()
+
+
+def test_batch_fused_matches_box_by_box():
+    """An FP32 ensemble with fused diagnostic steps (batched update, then one fix-up, cells,
+    overlap and reduction launch for all boxes) against the same ensemble running the
+    post-step kernels box by box: fields bitwise, windings, overlap and cells bitwise, sums
+    to rounding.  Box widths 64 and 128 take the packed-word overlap, the others the byte
+    one; guard cases are planted in one box."""
+    shapes = [(64, 9, 6), (24, 16, 12), (70, 9, 5), (128, 4, 4), (33, 20, 7)]
+    eras = [0.5, 2.0 / 3.0, 0.5, 2.0 / 3.0, 0.5]
+    s_b = [0.0, 1.0, 1.0, 0.0, 1.0]
+    kw = dict(precision="fp32", diag_every=2)
+    states = [I.to_f32_values(I.random_full(*sh, 50 + k, link=0.7, mom=0.4)) for k, sh in enumerate(shapes)]
+    states[0] = _planted(*shapes[0], 41)
+    runs = []
+    for rows in (8, 0):
+        bt = P.Batch([P.make_params(*sh, eta_ref=5.0 + k, **kw) for k, sh in enumerate(shapes)])
+        bt.set_fused_diagnostics(rows)
+        assert bt.get_fused_diagnostics() == rows
+        bt.set_tile(8, [4, 3, 5, 2, 7])
+        for k, st in enumerate(states):
+            bt.set_fields(k, st)
+        bt.step(5, [1.0] * len(shapes), eras, s_b)
+        runs.append(([bt.get_fields(k) for k in range(len(shapes))], [bt.diagnostics(k) for k in range(len(shapes))]))
+        bt.close()
+    (fa, ra), (fb, rb) = runs
+    for k in range(len(shapes)):
+        assert np.array_equal(fa[k], fb[k]), k
+        assert len(ra[k]) == len(rb[k]) == 3
+        for a, b in zip(ra[k], rb[k]):
+            assert a["wind_abs"] == b["wind_abs"] and a["pq_count2"] == b["pq_count2"], k
+            for q in SUMS:
+                assert a[q] == pytest.approx(b[q], rel=1e-11, abs=1e-11), (k, q)
+            for s in range(2):
+                assert a["gauss_abs"][s] == pytest.approx(b["gauss_abs"][s], rel=1e-11, abs=1e-12)
+                assert a["gauss_scale"][s] == pytest.approx(b["gauss_scale"][s], rel=1e-11)

@@ -47,19 +47,23 @@ def kernel_source_hash():
 def measured_traffic(n, precision, tile, nt, pf, pp=False, xcd=True):
     """HBM bytes per launch of the update kernel from the committed rocprofv3
     counter summary, if it was taken on this kernel source, tile shape, store
-    mode, load pipeline, momentum mode, tile order and workload; else None."""
+    mode, load pipeline, momentum mode, tile order and workload; else None.
+    Returns (bytes, source description) or (None, reason)."""
+    rel = os.path.relpath(TRAFFIC_FILE, ROOT)
     if n != 512 or precision != "fp32" or not os.path.exists(TRAFFIC_FILE):
-        return None
+        return None, f"no counter file for {n}^3 {precision}"
     lines = [l.strip() for l in open(TRAFFIC_FILE) if l.strip() and not l.startswith("#")]
     head = dict(l.split("=", 1) for l in lines if " " not in l and "=" in l)
-    if head.get("source_sha256") != kernel_source_hash():
-        return None
+    src = kernel_source_hash()
+    if head.get("source_sha256") != src:
+        return None, f"{rel} was taken on kernel source {head.get('source_sha256', '?')[:16]}, not {src[:16]}"
     want = f"{tile[0]},{tile[1]},{int(nt)},{int(pf)},{int(pp)},{int(xcd)}"
     for l in lines:
         kv = dict(f.split("=", 1) for f in l.split() if "=" in f)
         if kv.get("config") == want:
-            return int(kv["bytes_per_launch"])
-    return None
+            return int(kv["bytes_per_launch"]), f"{rel} (rocprofv3 FETCH_SIZE + WRITE_SIZE, config {want}, " \
+                                                 f"kernel source sha256 {src[:16]})"
+    return None, f"{rel} has no pass for config {want}"
 
 
 def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0.5, s=1.0, eta_ref=128.0, seed=1,
@@ -106,6 +110,11 @@ def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0
         launch_ms, per_launch, kname = tm["ms_plain"] / max(tm["n_plain"], 1), 1, "step_tile_kernel"
     kern_ms = launch_ms / per_launch
     achieved = BYTES_PER_SITE[precision] * sites * per_launch / (launch_ms * 1e-3) / 1e9
+    traffic, traffic_src = (measured_traffic(n, precision, lat.get_tile(), lat.get_streaming_stores(),
+                                             lat.get_prefetch(), lat.get_momentum_pingpong(), lat.get_tile_order())
+                            if per_launch == 1 else (None, "no counter pass for the two-step kernel"))
+    eta_first = eta0 + warmup * params.dt
+    eta_last = eta0 + (warmup + steps - 1) * params.dt
     out = {
         "value": sites * steps / wall,
         "ms_per_step": 1e3 * wall / steps,
@@ -115,13 +124,14 @@ def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0
         "roofline": {"bound": "hbm", "kernel": kname, "steps_per_launch": per_launch,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(n, precision, lat.get_tile(), lat.get_streaming_stores(),
-                                                lat.get_prefetch(), lat.get_momentum_pingpong(), lat.get_tile_order())
-                     if per_launch == 1 else None,
+                     "traffic": traffic, "traffic_source": traffic_src,
                      "algorithmic_bytes": BYTES_PER_SITE[precision] * sites,
                      "box_ceiling": {**{k: round(v, 1) for k, v in ceiling.items()},
                                      "frac_of_pattern": achieved / ceiling["pattern_GBps"]}},
         "pure_step_value": sites / (kern_ms * 1e-3),
+        "eta_timed": [eta_first, eta_last],
+        "diag_steps_timed": tm["n_diag"],
+        "fused_diagnostics_rows": lat.get_fused_diagnostics(),
         "tile": lat.get_tile(),
         "streaming_stores": lat.get_streaming_stores(),
         "prefetch": lat.get_prefetch(),
@@ -142,8 +152,9 @@ def run_batch(P, torch, steps, small=48, big=16, tune_steps=3):
     """Ensemble of uneven boxes: `small` boxes of 128^3 and `big` of 256^3; box b has seed
     1000 + b, m = 1/2 (b even) or 2/3 (b odd), s = 0 if b//2 is even else 1; all FP32, dx = 0.5,
     dt = 0.1, kappa = 0.9, diagnostics every 10 steps, `steps` steps from eta = 1 with a = 1 at
-    the end, all advanced by one graph launch; tile shape, streaming stores and momentum ping-pong from
-    the autotuner."""
+    the end, all advanced by one graph launch; tile shape, streaming stores, momentum ping-pong, tile
+    order and the persistent launch of the plain steps from the autotuner (both forms' plain-step
+    times reported)."""
     nb = small + big
     eta_end = 1.0 + steps * 0.1
     params = [P.make_params(128 if b < small else 256, precision="fp32", eta_ref=eta_end, diag_every=10)
@@ -168,6 +179,7 @@ def run_batch(P, torch, steps, small=48, big=16, tune_steps=3):
            "tile": [ty, tz], "streaming_stores": bt.get_streaming_stores(),
            "momentum_pingpong": bt.get_momentum_pingpong(),
            "tile_order": "xcd_runs" if bt.get_tile_order() else "round_robin", "autotune_ms_per_step": tune_ms,
+           "persistent": bt.get_persistent(), "autotune_plain_ms_per_step": bt.autotune_times(),
            "records_per_box": min(nrec),
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -178,19 +190,40 @@ def run_batch(P, torch, steps, small=48, big=16, tune_steps=3):
     return out
 
 
-def cpu_baseline():
-    """The FP64 oracle on a bounded sample of the workload: a 128^3 box with the same
-    schedule (radiation era, s = 1, a = 1 at eta = 128), 80 steps with the diagnostics
-    every 10th step (about 15 s of CPU work), on all host threads OpenMP gives it."""
+def cpu_baseline(full_steps=3):
+    """The FP64 oracle on bounded samples of the workload, on all host threads OpenMP gives
+    it: the 512^3 box itself (same schedule: radiation era, s = 1, a = 1 at eta = 128, random
+    phases of seed 1) for `full_steps` plain steps from eta = 1 (about 35 s of CPU work and
+    32 GB of host memory for three steps; an oracle diagnostic step at this size would hold
+    about 80 GB); a 128^3 box for 80 steps with the diagnostics every 10th step; and a 64^3
+    box on one thread."""
     import oracle as O
 
+    threads = O.num_threads()
+    out = {"unit": "site-updates/s", "cores": threads, "kind": "oracle"}
+    if full_steps:
+        n = 512
+        m = O.model(n, eta_ref=128.0)
+        st = O.init_random_phase(m, 1)
+        t0 = time.perf_counter()
+        O.run(m, st, full_steps, 1.0, 0.5, 1.0, diag_every=0)
+        dt = time.perf_counter() - t0
+        del st
+        out.update(value=n ** 3 * full_steps / dt,
+                   sample=f"{n}^3 box, {full_steps} plain steps from eta=1 (m=1/2, s=1), FP64, {dt:.1f} s on "
+                          f"{threads} threads")
     n, steps = 128, 80
     m = O.model(n, eta_ref=128.0)
     st = O.init_random_phase(m, 1)
     t0 = time.perf_counter()
     O.run(m, st, steps, 1.0, 0.5, 1.0, diag_every=10)
     dt = time.perf_counter() - t0
-    threads = O.num_threads()
+    small = {"value": n ** 3 * steps / dt, "unit": "site-updates/s", "cores": threads,
+             "sample": f"{n}^3 box, {steps} steps from eta=1 (m=1/2, s=1, diagnostics every 10), FP64, {dt:.1f} s"}
+    if "value" not in out:
+        out.update(value=small["value"], sample=small["sample"])
+    else:
+        out["sample_128"] = small
     # the same on one thread, on a smaller sample (about 3 s)
     n1, steps1 = 64, 10
     m1 = O.model(n1, eta_ref=128.0)
@@ -200,10 +233,18 @@ def cpu_baseline():
     O.run(m1, st1, steps1, 1.0, 0.5, 1.0, diag_every=10)
     dt1 = time.perf_counter() - t1
     O.set_num_threads(threads)
-    return {"value": n ** 3 * steps / dt, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n}^3 box, {steps} steps from eta=1 (m=1/2, s=1, diagnostics every 10), FP64, {dt:.1f} s",
-            "single_thread": {"value": n1 ** 3 * steps1 / dt1, "unit": "site-updates/s", "cores": 1,
-                              "sample": f"{n1}^3 box, {steps1} steps from eta=1 (same schedule), FP64, {dt1:.1f} s"}}
+    out["single_thread"] = {"value": n1 ** 3 * steps1 / dt1, "unit": "site-updates/s", "cores": 1,
+                            "sample": f"{n1}^3 box, {steps1} steps from eta=1 (same schedule), FP64, {dt1:.1f} s"}
+    return out
+
+
+def leg_summary(r, precision, n, steps, workload):
+    return {"workload": workload, "precision": precision, "sites": n ** 3, "steps": steps, "value": r["value"],
+            "unit": "site-updates/s", "ms_per_step": r["ms_per_step"], "kernel_ms": r["kernel_ms"],
+            "diag_step_kernel_ms": r["diag_step_kernel_ms"], "diag_post_ms": r["diag_post_ms"],
+            "eta_timed": r["eta_timed"], "tile": r["tile"], "fused_diagnostics_rows": r["fused_diagnostics_rows"],
+            "roofline": {k: r["roofline"][k] for k in ("bound", "achieved", "peak", "unit", "frac",
+                                                       "algorithmic_bytes", "box_ceiling")}}
 
 
 def copy_probe(torch, gib=2, reps=5):
@@ -239,6 +280,12 @@ def main():
                          "1/0: tiles in contiguous runs per XCD or round-robin)")
     ap.add_argument("--time-blocking", type=str, default=None,
                     help="steps,ty,tz: steps per sweep (1, or 2: the two-step kernel with 64 x ty x tz tiles), FP32 leg")
+    ap.add_argument("--cpu-full-steps", type=int, default=3,
+                    help="steps of the oracle's 512^3 sample in cpu_baseline (0: only the smaller samples)")
+    ap.add_argument("--legs", type=str, default="",
+                    help="comma list of extra legs: 1024 (1024^3 matter era, s=0, FP32 then FP64, no diagnostics) "
+                         "and/or 1280 (1280^3 radiation era, s=1, FP32, diagnostics every 50)")
+    ap.add_argument("--leg-steps", type=int, default=20)
     args = ap.parse_args()
     if args.source_hash:
         print(kernel_source_hash())
@@ -269,7 +316,27 @@ def main():
     if batch:
         print(f"batch: {batch['value']:.4g} site-updates/s, {batch['roofline']['frac']:.3f} of HBM peak, "
               f"tile {batch['tile']}", file=sys.stderr, flush=True)
-    cpu = None if args.no_cpu else cpu_baseline()
+    legs = {}
+    for leg in [v for v in args.legs.split(",") if v]:
+        if leg == "1024":
+            # 1024^3, matter era (m = 2/3), core growth s = 0 (the switch to s = 1 at eta = 32 lies beyond
+            # these steps), a = 1 at eta = 256, FP32 then FP64, no diagnostics (the configuration has none)
+            wl = "1024^3, matter era (m=2/3), s=0, a=1 at eta=256, no diagnostics"
+            for prec in ("fp32", "fp64"):
+                r = run_box(P, torch, 1024, prec, 5, args.leg_steps, diag_every=0, era_m=2.0 / 3.0, s=0.0,
+                            eta_ref=256.0)
+                legs[f"1024_{prec}"] = leg_summary(r, prec, 1024, args.leg_steps, wl)
+                print(f"leg 1024 {prec}: kernel {r['kernel_ms']:.2f} ms, {r['roofline']['frac']:.3f} of HBM peak",
+                      file=sys.stderr, flush=True)
+        elif leg == "1280":
+            wl = "1280^3, radiation era (m=1/2), s=1, a=1 at eta=201, diagnostics every 50"
+            r = run_box(P, torch, 1280, "fp32", 5, args.leg_steps, diag_every=50, eta_ref=201.0)
+            legs["1280_fp32"] = leg_summary(r, "fp32", 1280, args.leg_steps, wl)
+            print(f"leg 1280 fp32: kernel {r['kernel_ms']:.2f} ms, {r['roofline']['frac']:.3f} of HBM peak",
+                  file=sys.stderr, flush=True)
+        else:
+            raise SystemExit(f"bench.py: unknown leg {leg!r} (1024 or 1280)")
+    cpu = None if args.no_cpu else cpu_baseline(args.cpu_full_steps)
 
     line = {
         "metric": METRIC,
@@ -284,9 +351,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.n}^3 periodic box, radiation era (m=1/2), s=1, eta 1->128, dx=0.5, dt=0.1, "
-                               "lambda=2, e=1, sigma=1, kappa=0.9, random-phase ICs (seed 1), FP32 fields + FP64 "
-                               "reductions, diagnostics every 10 steps",
+        "config": {"workload": f"{args.n}^3 periodic box, radiation era (m=1/2), s=1, a=1 at eta=128, dx=0.5, "
+                               "dt=0.1, lambda=2, e=1, sigma=1, kappa=0.9, random-phase ICs (seed 1), FP32 fields + "
+                               f"FP64 reductions, diagnostics every 10 steps; timed {args.steps} steps from eta="
+                               f"{fp32['eta_timed'][0]:.1f} to {fp32['eta_timed'][1]:.1f} after {args.warmup} "
+                               "warm-up steps from eta=1 (the full configuration runs 1270 steps to eta=128)",
                    "sites": args.n ** 3},
         "roofline": fp32["roofline"],
         "cpu_baseline": cpu,
@@ -300,11 +369,14 @@ def main():
         "time_blocking": fp32["time_blocking"],
         "diag_step_kernel_ms": fp32["diag_step_kernel_ms"],
         "diag_post_ms": fp32["diag_post_ms"],
+        "diag_steps_timed": fp32["diag_steps_timed"],
+        "fused_diagnostics_rows": fp32["fused_diagnostics_rows"],
         "fp64": {"value": fp64["value"], "unit": "site-updates/s", "steps": args.fp64_steps,
                  "ms_per_step": fp64["ms_per_step"], "kernel_ms": fp64["kernel_ms"], "tile": fp64["tile"],
                  "streaming_stores": fp64["streaming_stores"], "tile_order": fp64["tile_order"],
                  "roofline": fp64["roofline"]} if fp64 else None,
         "batch": batch,
+        "legs": legs or None,
         "last_record": fp32["last_record"],
     }
     print(json.dumps(line), flush=True)

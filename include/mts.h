@@ -228,10 +228,10 @@ int mts_segments(mts_ctx *ctx, double min_length, mts_segments_t *out, int64_t *
 
 /* Choose the update kernel.  ty in {4, 5, 8, 12} (and 13 in FP32) selects
  * the z-marching LDS-tiled kernel with tiles of 64 x ty sites and tz >= 1
- * planes per workgroup (default 8 x 32 in FP32, 4 x 32 in FP64; FP32
- * diagnostic steps use at most 8 rows, where their variant does not spill
- * registers, and FP64 diagnostic steps the per-site kernel); every tile
- * shape gives bitwise identical results.  ty = 0 selects the one-thread-per-site kernel, which computes
+ * planes per workgroup (default 8 x 32 in FP32, 4 x 32 in FP64; diagnostic
+ * steps use at most 8 rows in FP32 and 4 in FP64, where their variant does
+ * not spill registers); every tile shape gives bitwise identical fields, and
+ * records that agree to the rounding of their block sums.  ty = 0 selects the one-thread-per-site kernel, which computes
  * the plaquette sines directly and agrees with the tiled kernel to
  * rounding.  Synchronises the stream.  EINVAL for other shapes. */
 int mts_set_tile(mts_ctx *ctx, int32_t ty, int32_t tz);
@@ -412,14 +412,37 @@ int mts_batch_get_fused_diagnostics(const mts_batch *b, int32_t *rows);
 int mts_batch_set_tile_order(mts_batch *b, int32_t xcd_runs);
 int mts_batch_get_tile_order(const mts_batch *b, int32_t *xcd_runs);
 
+/* Persistent launch of the plain steps (on != 0): every run of consecutive
+ * plain steps between two diagnostic steps of an mts_batch_step call is one
+ * launch whose workgroups stay resident (grid: the occupancy query of the
+ * current tile shape times the compute units, at most the tiles of a step)
+ * and loop over the steps, claiming tiles one at a time from a device
+ * counter, with a device-wide barrier after each step (the tile order setting
+ * does not apply); the diagnostic steps launch as before.  The tiles and
+ * their arithmetic are the per-step launches', so the results are the same
+ * bit for bit (Sec. III's leapfrog step, unchanged).  Every barrier wait is bounded by
+ * wait_limit_s seconds (0: 10 s; at most 3600): a wait that runs out (the grid
+ * was not co-resident, e.g. another kernel holds compute units, or a step is
+ * slower than the limit) makes every workgroup leave, and the next call that
+ * synchronises the batch (mts_batch_step, _timing_read, _diagnostics,
+ * _get_fields) returns MTS_EHIP once; the fields then hold an unfinished step
+ * and must be set again.  MTS_EINVAL for a limit out of range. */
+int mts_batch_set_persistent(mts_batch *b, int32_t on, double wait_limit_s);
+int mts_batch_get_persistent(const mts_batch *b, int32_t *on);
+
 /* Summed HIP-event time (ms) of the graph launches and the steps they ran
  * since the last read; synchronises. */
 int mts_batch_timing_read(mts_batch *b, int64_t *steps, double *ms);
 
 /* Autotuner of the batched launch (one ty and one tz for all boxes, streaming
- * stores, then momentum ping-pong and the tile order on the best of those),
- * as mts_autotune; overwrites every box. */
+ * stores, then momentum ping-pong, the tile order and the persistent launch
+ * on the best of those), as mts_autotune; overwrites every box. */
 int mts_batch_autotune(mts_batch *b, int32_t steps, int32_t *ty, int32_t *tz, double *ms_per_step);
+
+/* Per-step time (ms) of the plain steps the last mts_batch_autotune measured
+ * for its final configuration as per-step launches in one graph and as one
+ * persistent launch (0 before any autotune). */
+int mts_batch_autotune_times(const mts_batch *b, double *graph_ms, double *persistent_ms);
 
 const char *mts_batch_last_error(const mts_batch *b);
 

@@ -295,17 +295,19 @@ TileShape diag_tile(const mts_ctx *c) {
     return TileShape{std::min(c->tile.ty, cap), c->tile.tz};
 }
 
-// FP64 diagnostic steps run the one-thread-per-site kernel: the tiled DIAG
-// variant in double needs about 300 registers a thread and spills 60-90 of
-// them (512^3: 28.7 ms per diagnostic step against 22.5 ms per site, plus
-// 1.1 ms for the separate phase kernel).
-// Ensembles do the same for their FP64 diagnostic steps (one launch per box).
-bool diag_per_site(const mts_ctx *c) { return c->tile.ty == 0 || c->p.precision == MTS_FP64; }
+// Diagnostic steps run on the per-site kernel only where the plain steps do.
+bool diag_per_site(const mts_ctx *c) { return c->tile.ty == 0; }
+
+// The tiled FP32 diagnostic step writes the phases alpha of phi^n itself; the
+// per-site kernel and the FP64 tiled one leave them to the phase kernel.
+bool diag_writes_alpha(const mts_ctx *c) { return !diag_per_site(c) && c->p.precision == MTS_FP32; }
 
 // Diagnostic steps of the tiled FP32 kernel take the windings and the Gauss
 // residual in the same pass (the post-step kernels then only form the cells
 // and the overlap) unless switched off or no second momentum copy fits.
-bool diag_fused(const mts_ctx *c) { return !diag_per_site(c) && c->fuse_ty != 0 && !c->fuse_off; }
+bool diag_fused(const mts_ctx *c) {
+    return !diag_per_site(c) && c->p.precision == MTS_FP32 && c->fuse_ty != 0 && !c->fuse_off;
+}
 
 TileShape fused_tile(const mts_ctx *c) { return TileShape{c->fuse_ty, c->tile.tz}; }
 
@@ -413,7 +415,7 @@ int do_step(mts_ctx *c, int32_t n, double eta, double era_m, double s) {
         hipError_t ep = hipSuccess;
         if (diag) {
             TimedRegion tr(c, 2);
-            ep = enqueue_diag_post<T>(c, b, eta_j, s, c->stream, !diag_per_site(c), fused);
+            ep = enqueue_diag_post<T>(c, b, eta_j, s, c->stream, diag_writes_alpha(c), fused);
         }
         c->cur = 1 - c->cur;
         c->step_count++;
@@ -1279,6 +1281,10 @@ struct mts_batch {
     bool nt = true;                  // streaming stores in the tiled update
     bool mpp = false;                // plain tiled steps write the momenta to the other copy
     bool xcd = true;                 // tiles dealt to the XCDs in contiguous runs (else round-robin)
+    bool persist = false;            // runs of plain steps in one persistent launch (grid barrier per step)
+    GridSync *gsync = nullptr;       // the persistent kernel's barrier state
+    double persist_wait_s = 10.0;    // longest barrier wait before the launch gives up
+    double tune_graph_ms = 0.0, tune_persist_ms = 0.0;   // the autotuner's last per-step times of both forms
     void *coef_dev = nullptr;        // StepCoef<T>[n][nbox]
     size_t coef_cap = 0;             // bytes
     int32_t ty = 8;
@@ -1394,6 +1400,50 @@ void batch_collect_timing(mts_batch *b) {
     b->t_pending = false;
 }
 
+// After the batch's stream has drained: did a persistent launch give up at a
+// barrier?  Reported once (the flag is cleared); the fields of every box are
+// then those of an unfinished step.
+int batch_check_persist(mts_batch *b) {
+    if (!b->gsync) return MTS_OK;
+    GridSync h{};
+    BHIPCHK(b, hipMemcpy(&h, b->gsync, sizeof h, hipMemcpyDeviceToHost));
+    if (h.err == 0) return MTS_OK;
+    BHIPCHK(b, hipMemset(&b->gsync->err, 0, sizeof(int32_t)));
+    return bfail(b, MTS_EHIP,
+                 "persistent ensemble launch: a grid-barrier wait ran out (workgroups not co-resident, or a step "
+                 "slower than the wait limit); the fields hold an unfinished step");
+}
+
+// Launch of a run of nrun plain steps of every box as one persistent kernel
+// (after the kernel that clears its barrier state).
+template <typename T>
+hipError_t batch_persist_run(mts_batch *b, int32_t j0, int32_t nrun) {
+    const size_t nbox = b->box.size();
+    int grid = 0;
+    hipError_t e = persist_max_blocks(b->precision == MTS_FP64, b->ty, b->nt, &grid);
+    if (e != hipSuccess) return e;
+    if (grid <= 0) return hipErrorInvalidConfiguration;
+    grid = std::min<int>(grid, (int)b->nblk);   // no more workgroups than tiles
+    int dev = 0, khz = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess) return e;
+    PersistArgs<T> a{};
+    a.boxes = static_cast<const BatchBox<T> *>(b->boxes_dev);
+    a.nbox = (int32_t)nbox;
+    a.ntiles = b->nblk;
+    a.coef = static_cast<const StepCoef<T> *>(b->coef_dev) + (size_t)j0 * nbox;
+    a.nsteps = nrun;
+    a.parity0 = b->box[0]->cur;
+    a.mcur0 = b->box[0]->mcur;
+    a.mpp = b->mpp ? 1 : 0;
+    a.sync = b->gsync;
+    a.limit_ticks = (uint64_t)std::max(1.0, b->persist_wait_s * 1e3 * (double)khz);
+    e = launch_persist_reset(b->gsync, b->stream);
+    if (e == hipSuccess) e = launch_persist<T>(a, b->ty, b->nt, (uint32_t)grid, b->stream);
+    return e;
+}
+
 template <typename T>
 int batch_step_t(mts_batch *b, int32_t n, const double *eta0, const double *era_m, const double *s_before,
                  const double *s_after, const double *eta_switch) {
@@ -1428,6 +1478,7 @@ int batch_step_t(mts_batch *b, int32_t n, const double *eta0, const double *era_
     BHIPCHK(b, hipStreamSynchronize(b->stream));
     batch_collect_timing(b);
     batch_release_graph(b);
+    if (const int rc = batch_check_persist(b); rc != MTS_OK) return rc;
 
     // Host bookkeeping advances while the steps are captured; nothing runs
     // until the graph is launched, so a failure before that restores it.
@@ -1464,8 +1515,22 @@ int batch_step_t(mts_batch *b, int32_t n, const double *eta0, const double *era_
     for (int32_t j = 0; j < n && err == hipSuccess; j++) {
         mts_ctx *c0 = b->box[0];
         const bool diag = d > 0 && (c0->step_count % d) == 0;
+        if (!diag && b->persist) {
+            // the run of plain steps up to the next diagnostic step (or the end of the call)
+            int32_t r = 1;
+            while (j + r < n && !(d > 0 && (c0->step_count + r) % d == 0)) r++;
+            err = batch_persist_run<T>(b, j, r);
+            for (int32_t i = 0; i < r; i++)
+                for (mts_ctx *c : b->box) {
+                    c->cur = 1 - c->cur;
+                    c->step_count++;
+                    if (b->mpp) c->mcur = 1 - c->mcur;
+                }
+            j += r - 1;
+            continue;
+        }
         if (diag && diag_per_site(c0)) {
-            // FP64 diagnostic steps: the per-site kernel, box by box (as single contexts do)
+            // diagnostic steps of per-site boxes: the per-site kernel, box by box (as single contexts do)
             for (size_t k = 0; k < nbox && err == hipSuccess; k++) {
                 mts_ctx *c = b->box[k];
                 err = launch_step<T>(c->g, fields_of<T>(c, c->cur), fields_of<T>(c, 1 - c->cur), moms_of<T>(c),
@@ -1497,7 +1562,7 @@ int batch_step_t(mts_batch *b, int32_t n, const double *eta0, const double *era_
         } else if (diag) {
             for (size_t k = 0; k < nbox && err == hipSuccess; k++)
                 err = enqueue_diag_post<T>(b->box[k], books[k][j], eta0[k] + j * b->box[k]->p.dt, svals[k][j],
-                                           b->stream, !diag_per_site(b->box[k]));
+                                           b->stream, diag_writes_alpha(b->box[k]));
         }
         for (mts_ctx *c : b->box) {
             c->cur = 1 - c->cur;
@@ -1608,6 +1673,7 @@ int mts_batch_destroy(mts_batch *b) {
     (void)hipFree(b->boxes_diag_dev);
     (void)hipFree(b->post_dev);
     (void)hipFree(b->coef_dev);
+    (void)hipFree(b->gsync);
     for (hipEvent_t ev : {b->ev_in, b->ev_out, b->ev_t0, b->ev_t1})
         if (ev) (void)hipEventDestroy(ev);
     if (b->stream) (void)hipStreamDestroy(b->stream);
@@ -1645,11 +1711,19 @@ int mts_batch_step(mts_batch *b, int32_t n, const double *eta0, const double *er
 
 int mts_batch_diagnostics(mts_batch *b, int32_t box, mts_diag *out, int32_t max, int32_t *count) {
     if (!b || box < 0 || box >= (int32_t)b->box.size()) return MTS_EINVAL;
+    if (b->gsync) {
+        BHIPCHK(b, hipStreamSynchronize(b->stream));
+        if (const int rc = batch_check_persist(b); rc != MTS_OK) return rc;
+    }
     return mts_diagnostics(b->box[box], out, max, count);
 }
 
 int mts_batch_get_fields(mts_batch *b, int32_t box, double *host) {
     if (!b || box < 0 || box >= (int32_t)b->box.size()) return MTS_EINVAL;
+    if (b->gsync) {
+        BHIPCHK(b, hipStreamSynchronize(b->stream));
+        if (const int rc = batch_check_persist(b); rc != MTS_OK) return rc;
+    }
     return mts_get_fields(b->box[box], host);
 }
 
@@ -1735,6 +1809,39 @@ int mts_batch_set_tile_order(mts_batch *b, int32_t xcd_runs) {
     return MTS_OK;
 }
 
+int mts_batch_set_persistent(mts_batch *b, int32_t on, double wait_limit_s) {
+    if (!b) return MTS_EINVAL;
+    if (!(wait_limit_s >= 0.0) || wait_limit_s > 3600.0)
+        return bfail(b, MTS_EINVAL, "persistent ensemble launch: wait limit must be in [0, 3600] s");
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->user));
+    if (on && !b->gsync) {
+        BHIPCHK(b, hipMalloc(&b->gsync, sizeof(GridSync)));
+        BHIPCHK(b, hipMemset(b->gsync, 0, sizeof(GridSync)));
+    }
+    if (on) {
+        int grid = 0;
+        BHIPCHK(b, persist_max_blocks(b->precision == MTS_FP64, b->ty, b->nt, &grid));
+        if (grid <= 0) return bfail(b, MTS_EINVAL, "persistent ensemble launch: no co-resident grid for this tile");
+    }
+    b->persist = on != 0;
+    b->persist_wait_s = wait_limit_s > 0.0 ? wait_limit_s : 10.0;
+    return MTS_OK;
+}
+
+int mts_batch_get_persistent(const mts_batch *b, int32_t *on) {
+    if (!b || !on) return MTS_EINVAL;
+    *on = b->persist ? 1 : 0;
+    return MTS_OK;
+}
+
+int mts_batch_autotune_times(const mts_batch *b, double *graph_ms, double *persistent_ms) {
+    if (!b) return MTS_EINVAL;
+    if (graph_ms) *graph_ms = b->tune_graph_ms;
+    if (persistent_ms) *persistent_ms = b->tune_persist_ms;
+    return MTS_OK;
+}
+
 int mts_batch_get_tile_order(const mts_batch *b, int32_t *xcd_runs) {
     if (!b || !xcd_runs) return MTS_EINVAL;
     *xcd_runs = b->xcd ? 1 : 0;
@@ -1744,6 +1851,7 @@ int mts_batch_get_tile_order(const mts_batch *b, int32_t *xcd_runs) {
 int mts_batch_timing_read(mts_batch *b, int64_t *steps, double *ms) {
     if (!b) return MTS_EINVAL;
     BHIPCHK(b, hipStreamSynchronize(b->stream));
+    if (const int rc = batch_check_persist(b); rc != MTS_OK) return rc;
     batch_collect_timing(b);
     if (steps) *steps = b->t_steps;
     if (ms) *ms = b->t_ms;
@@ -1765,6 +1873,8 @@ int mts_batch_autotune(mts_batch *b, int32_t steps, int32_t *ty_out, int32_t *tz
     std::vector<uint64_t> seeds(nbox, 0);
     std::vector<double> eta(nbox, 1.0), era(nbox, 0.5), sv(nbox, 1.0);
     b->mpp = false;
+    b->persist = false;
+    b->tune_graph_ms = b->tune_persist_ms = 0.0;
     int rc = mts_batch_init_fields(b, seeds.data());
     double best = INFINITY;
     int pick_ty = b->ty, pick_tz = b->tz.empty() ? 32 : b->tz[0];
@@ -1831,12 +1941,34 @@ int mts_batch_autotune(mts_batch *b, int32_t steps, int32_t *ty_out, int32_t *tz
             b->xcd = cur;
         b->mpp = false;
     }
+    // and the persistent launch of the same configuration, kept if faster
+    bool pick_persist = false;
+    if (rc == MTS_OK) {
+        b->mpp = pick_mpp;
+        b->tune_graph_ms = best / steps;
+        int64_t ns = 0;
+        double ms = 0;
+        if ((rc = mts_batch_set_persistent(b, 1, 0.0)) == MTS_OK &&
+            (rc = mts_batch_step(b, 1, eta.data(), era.data(), sv.data(), nullptr, nullptr)) == MTS_OK &&
+            (rc = mts_batch_timing_read(b, &ns, &ms)) == MTS_OK &&
+            (rc = mts_batch_step(b, steps, eta.data(), era.data(), sv.data(), nullptr, nullptr)) == MTS_OK &&
+            (rc = mts_batch_timing_read(b, &ns, &ms)) == MTS_OK) {
+            b->tune_persist_ms = ms / steps;
+            if (ms < best) {
+                best = ms;
+                pick_persist = true;
+            }
+        }
+        b->persist = false;
+        b->mpp = false;
+    }
     for (size_t k = 0; k < nbox; k++) b->box[k]->p.diag_every = d[k];
     if (rc != MTS_OK) return rc;
     std::vector<int32_t> tzv(nbox, pick_tz);
     if ((rc = mts_batch_set_tile(b, pick_ty, tzv.data())) != MTS_OK) return rc;
     if ((rc = mts_batch_init_fields(b, seeds.data())) != MTS_OK) return rc;   // momenta back in copy 0
     if ((rc = mts_batch_set_momentum_pingpong(b, pick_mpp ? 1 : 0)) != MTS_OK) return rc;
+    b->persist = pick_persist;
     if (!pick_mpp && !b->fused) {                     // the second momentum copies are not needed
         BHIPCHK(b, hipStreamSynchronize(b->stream));
         for (mts_ctx *c : b->box) {

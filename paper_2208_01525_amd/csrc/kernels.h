@@ -182,6 +182,40 @@ template <typename T>
 hipError_t launch_post_batch(const BatchPost<T> *boxes_dev, int nbox, uint32_t nfix, uint32_t ncells, uint32_t nov,
                              int parity, uint32_t ring_idx, hipStream_t st);
 
+// ---- persistent ensemble kernel: a run of plain steps of every box in one launch
+//
+// Device state of the grid barrier.  count and err are cleared by
+// launch_persist_reset before each launch (a kernel, so that a captured graph
+// holds no memset node); gen only ever grows.
+struct GridSync {
+    uint32_t count;              // workgroups arrived at the current barrier
+    uint32_t gen;                // barriers completed
+    int32_t err;                 // 1: a barrier wait ran out (the grid was not co-resident)
+    uint32_t pad;
+    unsigned long long next;     // tiles claimed so far in this launch (step j's are j ntiles ...)
+};
+
+template <typename T>
+struct PersistArgs {
+    const BatchBox<T> *boxes;    // the plain-step tile table (rows ty)
+    int32_t nbox;
+    uint32_t ntiles;             // tiles of all boxes per step
+    const StepCoef<T> *coef;     // [nsteps][nbox]
+    int32_t nsteps;
+    int32_t parity0, mcur0;      // field copy and momentum copy read by the first step
+    int32_t mpp;                 // momenta to the other copy every step (else in place)
+    GridSync *sync;
+    uint64_t limit_ticks;        // longest barrier wait, in wall-clock ticks
+};
+
+// Largest co-resident grid of the persistent kernel of this shape on the
+// current device (occupancy query times the compute units); 0 for a shape
+// it does not support.
+hipError_t persist_max_blocks(bool fp64, int ty, bool nt, int *blocks);
+hipError_t launch_persist_reset(GridSync *sync, hipStream_t st);
+template <typename T>
+hipError_t launch_persist(const PersistArgs<T> &a, int ty, bool nt, uint32_t grid, hipStream_t st);
+
 // Phase alpha = arg(phi) of every site and sector into alpha[2][plane]
 // (NaN where phi = 0), input of the winding kernel.
 template <typename T>

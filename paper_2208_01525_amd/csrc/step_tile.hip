@@ -182,6 +182,17 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
     T alc[2], ezp[2];
     int wxy[2];
     const int it = w * 64 + lx;            // interior thread's slot in FL
+    // FP64 diagnostic steps keep their six running sums in LDS, one slot per
+    // interior thread (same operations, same order): in registers they would
+    // push the z-march past 256 VGPRs
+    constexpr bool ACC_LDS = DIAG && !FUSE && sizeof(T) == 8;
+    __shared__ double accs[ACC_LDS ? 6 : 1][ACC_LDS ? 64 * TY : 1];
+    if constexpr (ACC_LDS) {
+        if (interior) {
+#pragma unroll
+            for (int q = 0; q < 6; q++) accs[q][it] = 0.0;
+        }
+    }
     auto load_raw = [&](int zz, cx<T> (&f)[2], T (&A)[2][3]) {
         const uint32_t s = colidx + g.nxy * (uint32_t)zz;
 #pragma unroll
@@ -310,8 +321,12 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
         }
         __syncthreads();
 
-        // own plaquette phasors of plane z
+        // own plaquette phasors of plane z (a non-fused diagnostic step folds
+        // its magnetic term in here, in the same order, so the cosines need not
+        // stay live through the update)
+        constexpr bool EARLY_B = DIAG && !FUSE;
         T sn[2][3], cs[2][3];
+        T Bg = 0;
 #pragma unroll
         for (int sec = 0; sec < 2; sec++) {
             own_plaquettes(cU[sec][0], cU[sec][1], cU[sec][2], ldc(L, sec, Q_UYR, lxp), ldc(L, sec, Q_UXR, lyp),
@@ -322,6 +337,8 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                 L.v[sec][Q_SXZ][li] = sn[sec][1];
                 L.v[sec][Q_SYZ][li] = sn[sec][2];
             }
+            if constexpr (EARLY_B)
+                Bg += c.inv_e2h4[sec] * (((T(1) - cs[sec][0]) + (T(1) - cs[sec][1])) + (T(1) - cs[sec][2]));
         }
         // fused: wrap counts of the x and y links of plane z+1 and of the z
         // link of plane z (garbage where the neighbour lies outside the tile:
@@ -388,7 +405,7 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
         }
 
         if (upd) {
-            T Kd = 0, Gd = 0, Kg = 0, Bg = 0, mod2[2] = {0, 0};
+            T Kd = 0, Gd = 0, Kg = 0, mod2[2] = {0, 0};
 #pragma unroll
             for (int sec = 0; sec < 2; sec++) {
                 SiteIn<T> q;
@@ -446,7 +463,8 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                     const T ebx = T(0.5) * (e0[sec][0] + r.e1[0]), eby = T(0.5) * (e0[sec][1] + r.e1[1]),
                             ebz = T(0.5) * (e0[sec][2] + r.e1[2]);
                     Kg += c.inv_2e2[sec] * ((ebx * ebx + eby * eby) + ebz * ebz);
-                    Bg += c.inv_e2h4[sec] * (((T(1) - cs[sec][0]) + (T(1) - cs[sec][1])) + (T(1) - cs[sec][2]));
+                    if constexpr (!EARLY_B)
+                        Bg += c.inv_e2h4[sec] * (((T(1) - cs[sec][0]) + (T(1) - cs[sec][1])) + (T(1) - cs[sec][2]));
                     mod2[sec] = r.m2;
                 }
                 if constexpr (FUSE) {
@@ -457,8 +475,9 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                 }
             }
             if constexpr (DIAG) {
-                if constexpr (!FUSE) {
-                    // phase of phi^n for the winding kernel (NaN where phi = 0)
+                if constexpr (!FUSE && sizeof(T) == 4) {
+                    // phase of phi^n for the winding kernel (NaN where phi = 0); in
+                    // FP64 the phase kernel writes them (its atan2 here would spill)
 #pragma unroll
                     for (int sec = 0; sec < 2; sec++)
                         st_stream<NT>(alpha + (size_t)sec * plane + s, phase_of(cf[sec]));
@@ -469,12 +488,14 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                 const T eps = (Kd + Gd) + c.am2s * (Kg + Bg) + c.a2s * V;
                 const T lag = (Kd - Gd) + c.am2s * (Kg - Bg) - c.a2s * V;
                 const double K = Kd, G = Gd, Lg = lag, Vi = Vint;
-                acc[0] += (double)eps;
-                acc[1] += Lg;
-                acc[2] += K * Lg;
-                acc[3] += G * Lg;
-                acc[4] += K * Vi;
-                acc[5] += G * Vi;
+                double *a0 = ACC_LDS ? &accs[0][it] : &acc[0];
+                constexpr int AS = ACC_LDS ? 64 * TY : 1;   // stride between the six sums
+                a0[0] += (double)eps;
+                a0[AS] += Lg;
+                a0[2 * AS] += K * Lg;
+                a0[3 * AS] += G * Lg;
+                a0[4 * AS] += K * Vi;
+                a0[5 * AS] += G * Vi;
             }
         }
         __syncthreads();   // LDS of plane z is reused by plane z+1
@@ -511,6 +532,12 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                 cA[sec][i] = nA[sec][i];
                 cU[sec][i] = nU[sec][i];
             }
+        }
+    }
+    if constexpr (ACC_LDS) {
+        if (interior) {
+#pragma unroll
+            for (int q = 0; q < 6; q++) acc[q] = accs[q][it];
         }
     }
     if constexpr (FUSE) {
@@ -652,12 +679,11 @@ static hipError_t launch_ty(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> 
         // ahead: at the row counts they run with it costs no occupancy and
         // saves about 5 % (512^3: 4.82 against 5.08 ms).  The FP64 variant
         // is at its register limit already.  Diagnostic steps run at most 8
-        // rows in FP32 and on the per-site kernel in FP64, so the shapes
-        // only plain steps use have no diagnostic variant.  With wabs the
-        // windings and the Gauss residual are fused in (FP32; momenta out of
-        // place).
+        // rows in FP32 and 4 in FP64, so the shapes only plain steps use have
+        // no diagnostic variant.  With wabs the windings and the Gauss
+        // residual are fused in (FP32; momenta out of place).
         constexpr int DPF = sizeof(T) == 4 ? 1 : 0;
-        if constexpr (TY == 13 || (TY == 5 && sizeof(T) == 8)) {
+        if constexpr (TY == 13 || (TY != 4 && sizeof(T) == 8)) {
             return hipErrorNotSupported;
         } else {
             if (wabs) {
@@ -731,7 +757,7 @@ hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32
 #define MTS_BATCH_CASE(TYV)                                           \
     case TYV:                                                         \
         if (diag) {                                                   \
-            if constexpr (TYV == 13 || (TYV == 5 && sizeof(T) == 8)) {  \
+            if constexpr (TYV == 13 || (TYV != 4 && sizeof(T) == 8)) {  \
                 return hipErrorNotSupported;                          \
             } else {                                                  \
                 if (nt) MTS_BATCH_LAUNCH(TYV, true, true, false);     \
@@ -774,5 +800,239 @@ template hipError_t launch_step_tile<float>(const Geom &, Fields<float>, Fields<
 template hipError_t launch_step_tile<double>(const Geom &, Fields<double>, Fields<double>, Moms<double>, Moms<double>,
                                              const StepCoef<double> &, bool, Partials, TileShape, double *, uint8_t *,
                                              uint32_t, bool, bool, bool, hipStream_t);
+
+
+// ===================================================================== persistent ensemble kernel
+//
+// A run of plain steps of every box of an ensemble in one launch: the
+// workgroups stay resident and loop over the steps; in each step they claim
+// the tiles of every box (the plain-step tile table) one at a time and then
+// meet at a device-wide barrier before the next step reads what this one
+// wrote.  The arithmetic is the per-step launches': the same tile function on
+// the same tiles, so the fields come out bit for bit the same.  Diagnostic
+// steps are not part of it (their fused tile needs every register a wave may
+// hold; the loop state of this kernel would make it spill).
+
+namespace {
+
+// Wait until every workgroup of the grid has arrived.  The last one to arrive
+// sets the arrival count back to zero and advances the generation.  A wait
+// that outlasts limit_ticks (some workgroup never arrives: a grid larger than
+// what stays resident) raises the error flag, and every workgroup then leaves
+// at its next barrier instead of waiting for ever.  The agent-scope fences
+// make each workgroup's stores visible to the other XCDs before it arrives,
+// and theirs to it once it leaves.  Returns false once the flag is up.
+__device__ __forceinline__ bool grid_sync(GridSync *gs, uint32_t nblocks, uint32_t &gen, uint64_t limit_ticks) {
+    __shared__ int s_ok;
+    __threadfence();   // every thread: its stores of this step, visible at agent scope
+    __syncthreads();
+    if (threadIdx.x == 0 && threadIdx.y == 0) {
+        int ok = 1;
+        const uint32_t g = gen;
+        if (atomicAdd(&gs->count, 1u) == nblocks - 1) {
+            atomicExch(&gs->count, 0u);
+            __threadfence();
+            atomicAdd(&gs->gen, 1u);
+        } else {
+            const uint64_t t0 = (uint64_t)wall_clock64();
+            while (__hip_atomic_load(&gs->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (__hip_atomic_load(&gs->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    ok = 0;
+                    break;
+                }
+                if ((uint64_t)wall_clock64() - t0 > limit_ticks) {
+                    atomicExch(&gs->err, 1);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __threadfence();
+        if (__hip_atomic_load(&gs->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) ok = 0;
+        s_ok = ok;
+    }
+    gen++;
+    __syncthreads();
+    __threadfence();   // every thread: the other workgroups' stores, visible from here on
+    return s_ok != 0;
+}
+
+// A read of host-written tables (the box table, the coefficients) that no
+// kernel writes: through the constant address space, so that the compiler
+// takes the wave-uniform value into scalar registers (and may load it again
+// rather than hold it) although the kernel stores elsewhere in its loops.
+template <typename V>
+__device__ __forceinline__ V ld_uniform(const V *p) {
+    static_assert(sizeof(V) % 4 == 0, "whole words");
+    const __attribute__((address_space(4))) uint32_t *s = (const __attribute__((address_space(4))) uint32_t *)p;
+    uint32_t w[sizeof(V) / 4];
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(V) / 4); i++) w[i] = s[i];
+    V v;
+    __builtin_memcpy(&v, w, sizeof(V));
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ Fields<T> fields_global(Fields<T> f) {
+#pragma unroll
+    for (int sec = 0; sec < 2; sec++) {
+        f.phi[sec] = as_global(f.phi[sec]);
+#pragma unroll
+        for (int i = 0; i < 3; i++) f.A[sec][i] = as_global(f.A[sec][i]);
+    }
+    return f;
+}
+
+template <typename T>
+__device__ __forceinline__ Moms<T> moms_global(Moms<T> m) {
+#pragma unroll
+    for (int sec = 0; sec < 2; sec++) {
+        m.pi[sec] = as_global(m.pi[sec]);
+#pragma unroll
+        for (int i = 0; i < 3; i++) m.E[sec][i] = as_global(m.E[sec][i]);
+    }
+    return m;
+}
+
+}  // namespace
+
+// waves per SIMD the per-step launch of the same shape reaches; the loop state
+// must not cost the persistent kernel any of them
+template <typename T, int TY>
+constexpr int persist_waves() {
+    return sizeof(T) == 4 ? 4 : (TY <= 5 ? 2 : (TY == 8 ? 3 : 4));
+}
+
+// The next tile index for this workgroup (thread 0 claims it, all read it).
+__device__ __forceinline__ unsigned long long persist_claim(GridSync *gs) {
+    __shared__ unsigned long long s_idx;
+    if (threadIdx.x == 0 && threadIdx.y == 0) s_idx = atomicAdd(&gs->next, 1ull);
+    __syncthreads();
+    const unsigned long long v = s_idx;
+    __syncthreads();
+    return v;
+}
+
+template <typename T, int TY, bool NT>
+__global__ __launch_bounds__(64 * (TY + 3)) __attribute__((amdgpu_waves_per_eu(persist_waves<T, TY>())))
+void persist_plain_kernel(PersistArgs<T> a) {
+    __shared__ Lds<T, TY, NQ> L;
+    NoFusedLds<T, TY> nofl;
+    uint32_t gen = __hip_atomic_load(&a.sync->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // Tiles are claimed one at a time from a counter that runs through every
+    // step's tiles in turn (step j owns [j ntiles, (j + 1) ntiles)).  A
+    // workgroup stops a step at its first claim past the step's range and
+    // keeps that index for the step it belongs to, so every index is taken
+    // exactly once and no tile waits for a slow neighbour's share.
+    unsigned long long idx = persist_claim(a.sync);
+    for (int j = 0; j < a.nsteps; j++) {
+        if (j > 0 && !grid_sync(a.sync, gridDim.x, gen, a.limit_ticks)) return;
+        const int parity = (a.parity0 + j) & 1;
+        const int mpin = a.mpp ? (a.mcur0 + j) & 1 : a.mcur0, mpout = a.mpp ? 1 - mpin : mpin;
+        const unsigned long long first = (unsigned long long)j * a.ntiles, end = first + a.ntiles;
+        while (idx >= first && idx < end) {
+            const uint32_t t = (uint32_t)(idx - first);
+            int lo = 0, hi = a.nbox - 1;   // last box with blk0 <= t
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (ld_uniform(&a.boxes[mid].blk0) <= t) lo = mid;
+                else hi = mid - 1;
+            }
+            const BatchBox<T> *bx = a.boxes + lo;
+            const Geom g = ld_uniform(&bx->g);
+            const uint32_t lt = t - ld_uniform(&bx->blk0);
+            const int ntx = ld_uniform(&bx->ntx), nty = ld_uniform(&bx->nty), TZ = ld_uniform(&bx->tz);
+            const int tx = lt % ntx, ty_ = (lt / ntx) % nty, tz = lt / (ntx * nty);
+            const Fields<T> fin = fields_global(ld_uniform(&bx->f[parity]));
+            const Fields<T> fout = fields_global(ld_uniform(&bx->f[1 - parity]));
+            const Moms<T> mom = moms_global(ld_uniform(&bx->mom[mpin]));
+            const Moms<T> mom_out = moms_global(ld_uniform(&bx->mom[mpout]));
+            const StepCoef<T> c = ld_uniform(&a.coef[(size_t)j * a.nbox + lo]);
+            double acc[6] = {};
+            tile_step<T, false, TY, NT>(g, fin, fout, mom, mom_out, c, tx * 64, ty_ * TY, tz * TZ, TZ, L, acc,
+                                        nullptr, nullptr, ld_uniform(&bx->plane), nofl);
+            idx = persist_claim(a.sync);
+        }
+    }
+}
+
+__global__ void persist_reset_kernel(GridSync *gs) {
+    gs->count = 0u;
+    gs->err = 0;
+    gs->next = 0ull;
+}
+
+hipError_t launch_persist_reset(GridSync *sync, hipStream_t st) {
+    persist_reset_kernel<<<1, 1, 0, st>>>(sync);
+    return hipGetLastError();
+}
+
+namespace {
+
+template <typename T, int TY, bool NT>
+hipError_t persist_blocks_t(int *per) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, persist_plain_kernel<T, TY, NT>, 64 * (TY + 3), 0);
+}
+
+template <typename T, int TY>
+hipError_t persist_launch_t(const PersistArgs<T> &a, bool nt, uint32_t grid, hipStream_t st) {
+    const dim3 block(64, TY + 3, 1);
+    if (nt) persist_plain_kernel<T, TY, true><<<grid, block, 0, st>>>(a);
+    else persist_plain_kernel<T, TY, false><<<grid, block, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t persist_max_blocks(bool fp64, int ty, bool nt, int *blocks) {
+    int dev = 0, cus = 0, per = 0;
+    *blocks = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+#define MTS_PERSIST_Q(TV, TYV) (nt ? persist_blocks_t<TV, TYV, true>(&per) : persist_blocks_t<TV, TYV, false>(&per))
+    if (fp64) {
+        switch (ty) {
+            case 4: e = MTS_PERSIST_Q(double, 4); break;
+            case 5: e = MTS_PERSIST_Q(double, 5); break;
+            case 8: e = MTS_PERSIST_Q(double, 8); break;
+            case 12: e = MTS_PERSIST_Q(double, 12); break;
+            default: return hipSuccess;
+        }
+    } else {
+        switch (ty) {
+            case 4: e = MTS_PERSIST_Q(float, 4); break;
+            case 5: e = MTS_PERSIST_Q(float, 5); break;
+            case 8: e = MTS_PERSIST_Q(float, 8); break;
+            case 12: e = MTS_PERSIST_Q(float, 12); break;
+            case 13: e = MTS_PERSIST_Q(float, 13); break;
+            default: return hipSuccess;
+        }
+    }
+#undef MTS_PERSIST_Q
+    if (e != hipSuccess) return e;
+    *blocks = cus * per;
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_persist(const PersistArgs<T> &a, int ty, bool nt, uint32_t grid, hipStream_t st) {
+    if (grid == 0) return hipErrorInvalidValue;
+    switch (ty) {
+        case 4: return persist_launch_t<T, 4>(a, nt, grid, st);
+        case 5: return persist_launch_t<T, 5>(a, nt, grid, st);
+        case 8: return persist_launch_t<T, 8>(a, nt, grid, st);
+        case 12: return persist_launch_t<T, 12>(a, nt, grid, st);
+        case 13:
+            if constexpr (sizeof(T) == 4) return persist_launch_t<T, 13>(a, nt, grid, st);
+            else return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_persist<float>(const PersistArgs<float> &, int, bool, uint32_t, hipStream_t);
+template hipError_t launch_persist<double>(const PersistArgs<double> &, int, bool, uint32_t, hipStream_t);
 
 }  // namespace mts

@@ -27,7 +27,7 @@ EXPORTS = ("mts_state_bytes", "mts_create", "mts_destroy", "mts_init_fields", "m
            "mts_batch_init_fields", "mts_batch_step", "mts_batch_diagnostics", "mts_batch_get_fields",
            "mts_batch_set_fields", "mts_batch_set_tile", "mts_batch_set_streaming_stores", "mts_batch_get_streaming_stores", "mts_batch_set_momentum_pingpong",
            "mts_batch_get_momentum_pingpong", "mts_batch_set_fused_diagnostics", "mts_batch_get_fused_diagnostics", "mts_batch_set_tile_order", "mts_batch_get_tile_order", "mts_batch_timing_read", "mts_batch_autotune",
-           "mts_batch_last_error")
+           "mts_batch_set_persistent", "mts_batch_get_persistent", "mts_batch_autotune_times", "mts_batch_last_error")
 
 
 class Params(ctypes.Structure):
@@ -124,6 +124,9 @@ def load():
     L.mts_batch_get_fused_diagnostics.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.mts_batch_set_tile_order.argtypes = [vp, ctypes.c_int32]
     L.mts_batch_get_tile_order.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.mts_batch_set_persistent.argtypes = [vp, ctypes.c_int32, ctypes.c_double]
+    L.mts_batch_get_persistent.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.mts_batch_autotune_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.mts_get_tile.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     i32p = ctypes.POINTER(ctypes.c_int32)
     L.mts_autotune.argtypes = [vp, ctypes.c_int32, i32p, i32p, ctypes.POINTER(ctypes.c_double)]
@@ -493,6 +496,22 @@ class Batch:
         v = ctypes.c_int32()
         self._check(self.L.mts_batch_get_momentum_pingpong(self.b, ctypes.byref(v)))
         return bool(v.value)
+
+    def set_persistent(self, on, wait_limit_s=0.0):
+        """Runs of plain steps as one persistent launch (a grid barrier per step); wait_limit_s
+        bounds each barrier wait (0: 10 s)."""
+        self._check(self.L.mts_batch_set_persistent(self.b, 1 if on else 0, float(wait_limit_s)))
+
+    def get_persistent(self):
+        v = ctypes.c_int32()
+        self._check(self.L.mts_batch_get_persistent(self.b, ctypes.byref(v)))
+        return bool(v.value)
+
+    def autotune_times(self):
+        """Per-step ms of the per-step graph and of the persistent launch, as the last autotune timed them."""
+        g, p = ctypes.c_double(), ctypes.c_double()
+        self._check(self.L.mts_batch_autotune_times(self.b, ctypes.byref(g), ctypes.byref(p)))
+        return {"graph_ms": g.value, "persistent_ms": p.value}
 
     def timing_read(self):
         st, ms = ctypes.c_int64(), ctypes.c_double()

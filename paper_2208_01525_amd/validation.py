@@ -15,7 +15,17 @@ method for the pq lengths).
 
 Command line (one JSON line per run, then one summary line per era):
 
-    python -m paper_2208_01525_amd.validation --n 1024 --era 0.5 --seeds 1 2 3
+    python -m paper_2208_01525_amd.validation --n 1024 --era 0.5 --seeds 1 2 3 --records runs.jsonl
+
+--records appends the records of each run's averaging window as JSON lines;
+--summarize recomputes the per-seed values and the table of means and
+standard deviations from such files alone (no GPU):
+
+    python -m paper_2208_01525_amd.validation --summarize runs.jsonl
+
+The table also gives the separation slopes under the other reading of the
+string length (a Manhattan-length correction of 2/3 on L, which scales every
+xi and its slope by sqrt(3/2)), labelled as that reading.
 """
 import argparse
 import json
@@ -81,6 +91,52 @@ def run(n, era_m, seed, m_damp=0.9, dx=0.5, dt=0.1, diag_every=10, eta_lo=230.0,
     return records, asymptotic(records, eta_lo, eta_end)
 
 
+SUMMARY_KEYS = ("v2_lag", "v2_pq", "xi_W_dot", "xi_p_dot", "xi_pq_dot", "xi_lag_dot", "f_total", "f_p")
+MANHATTAN = math.sqrt(1.5)   # xi under L -> (2/3) L
+
+
+def summarize(per_seed):
+    """Mean and sample standard deviation over seeds of each asymptotic value."""
+    out = {"seeds": len(per_seed)}
+    for key in SUMMARY_KEYS:
+        v = np.array([s[key] for s in per_seed if s.get(key) is not None], dtype=np.float64)
+        if v.size:
+            out[key] = [float(v.mean()), float(v.std(ddof=1)) if v.size > 1 else math.nan]
+    return out
+
+
+def summarize_files(paths, eta_lo=230.0):
+    """Per-seed asymptotic values and the per-(n, era) summary from record files."""
+    runs = {}
+    for path in paths:
+        with open(path) as f:
+            for line in f:
+                r = json.loads(line)
+                runs.setdefault((r["n"], r["era"], r["seed"]), []).append(r)
+    groups = {}
+    for (n, era, seed), recs in sorted(runs.items()):
+        recs.sort(key=lambda r: r["eta"])
+        lo = eta_lo if n == 1024 else eta_lo * n / 1024.0
+        asym = asymptotic(recs, lo, recs[-1]["eta"])
+        groups.setdefault((n, era), []).append({"seed": seed, **asym})
+    return groups
+
+
+def table(groups):
+    """Markdown rows: era, quantity, mean +- std (and the sqrt(3/2) reading of the slopes)."""
+    rows = ["| n | era | quantity | mean ± std over seeds | with L → (2/3) L |", "|---|---|---|---|---|"]
+    for (n, era), per_seed in sorted(groups.items()):
+        sm = summarize(per_seed)
+        name = "radiation" if abs(era - 0.5) < 1e-9 else ("matter" if abs(era - 2.0 / 3.0) < 1e-6 else f"m={era}")
+        for key in SUMMARY_KEYS:
+            if key not in sm:
+                continue
+            m, sd = sm[key]
+            alt = f"{m * MANHATTAN:.4g} ± {sd * MANHATTAN:.2g}" if key.startswith("xi_") else ""
+            rows.append(f"| {n} | {name} ({sm['seeds']} seeds) | {key} | {m:.4g} ± {sd:.2g} | {alt} |")
+    return "\n".join(rows)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--n", type=int, default=1024)
@@ -88,8 +144,19 @@ def main(argv=None):
     ap.add_argument("--m-damp", type=float, default=0.9)
     ap.add_argument("--seeds", type=int, nargs="+", default=[1])
     ap.add_argument("--eta-lo", type=float, default=230.0)
-    ap.add_argument("--records", type=str, default=None, help="write every record as JSON lines here")
+    ap.add_argument("--records", type=str, default=None,
+                    help="append the records of each run's averaging window here (JSON lines)")
+    ap.add_argument("--summarize", type=str, nargs="+", default=None,
+                    help="record files to summarise (no runs)")
     a = ap.parse_args(argv)
+    if a.summarize:
+        groups = summarize_files(a.summarize, a.eta_lo)
+        for (n, era), per_seed in sorted(groups.items()):
+            for ps in per_seed:
+                print(json.dumps({"n": n, "era": era, **ps}), flush=True)
+            print(json.dumps({"summary": {"n": n, "era": era, **summarize(per_seed)}}), flush=True)
+        print(table(groups), flush=True)
+        return
     per_seed = []
     rec_file = open(a.records, "a") if a.records else None
     for seed in a.seeds:
@@ -97,17 +164,13 @@ def main(argv=None):
         records, asym = run(a.n, a.era, seed, m_damp=a.m_damp, eta_lo=eta_lo)
         if rec_file:
             for r in records:
-                rec_file.write(json.dumps({"n": a.n, "era": a.era, "seed": seed, **r}) + "\n")
+                if r["eta"] >= eta_lo:
+                    rec_file.write(json.dumps({"n": a.n, "era": a.era, "m_damp": a.m_damp, "seed": seed, **r}) + "\n")
             rec_file.flush()
         line = {"n": a.n, "era": a.era, "m_damp": a.m_damp, "seed": seed, **asym}
         print(json.dumps(line), flush=True)
         per_seed.append(asym)
-    summary = {"n": a.n, "era": a.era, "seeds": len(per_seed)}
-    for key in ("v2_lag", "v2_pq", "xi_W_dot", "xi_p_dot", "xi_pq_dot", "xi_lag_dot", "f_total"):
-        v = np.array([s[key] for s in per_seed if s.get(key) is not None], dtype=np.float64)
-        if v.size:
-            summary[key] = [float(v.mean()), float(v.std(ddof=1)) if v.size > 1 else math.nan]
-    print(json.dumps({"summary": summary}), flush=True)
+    print(json.dumps({"summary": {"n": a.n, "era": a.era, **summarize(per_seed)}}), flush=True)
 
 
 if __name__ == "__main__":

@@ -34,3 +34,29 @@ def test_asymptotic_empty_window():
 
 def approx(x):
     return pytest.approx(x, rel=1e-12, abs=1e-12)
+
+
+def test_summarize_files_recomputes_per_seed_values(tmp_path):
+    """Record files alone give the per-seed slopes and the mean +- std table; the
+    Manhattan-length reading scales only the separation slopes, by sqrt(3/2)."""
+    import json
+
+    path = tmp_path / "runs.jsonl"
+    slopes = {1: 0.20, 2: 0.22, 3: 0.18}
+    with open(path, "w") as f:
+        for seed, k in slopes.items():
+            for e in range(230, 257):
+                r = _rec(float(e), k * e + seed, 0.25 + 0.01 * seed)
+                f.write(json.dumps({"n": 1024, "era": 0.5, "m_damp": 0.9, "seed": seed, **r}) + "\n")
+    groups = V.summarize_files([str(path)])
+    per_seed = groups[(1024, 0.5)]
+    assert [p["seed"] for p in per_seed] == [1, 2, 3]
+    assert [p["xi_W_dot"] for p in per_seed] == [approx(0.20), approx(0.22), approx(0.18)]
+    sm = V.summarize(per_seed)
+    assert sm["xi_W_dot"][0] == approx(0.20) and sm["xi_W_dot"][1] == approx(0.02)
+    assert sm["f_p"][0] == approx(0.04) and sm["v2_lag"][0] == approx(0.27)
+    t = V.table(groups)
+    row = next(line for line in t.splitlines() if "| xi_W_dot |" in line)
+    assert f"{0.2 * math.sqrt(1.5):.4g}" in row
+    vrow = next(line for line in t.splitlines() if "| v2_lag |" in line)
+    assert vrow.rstrip().endswith("|  |")

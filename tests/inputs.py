@@ -102,3 +102,21 @@ def string_set(nx, ny, nz, p_vortices=(), q_vortices=(), sig=(1.0, 1.0)):
         st[c] = (sig[sec] * np.cos(th))[None]
         st[c + 1] = (sig[sec] * np.sin(th))[None]
     return st
+
+
+def ring(nx, ny, nz, radius, center=None):
+    """One closed string in the p sector: a circle of the given radius (lattice units) in
+    the plane z = cz about (cx, cy); the phase at a point is the polar angle of (rho - R,
+    z - cz) in the half-plane through the ring's axis (rho its distance from the axis),
+    so it winds once around the core; modulus 1.  The default centre lies at half-integer
+    coordinates so the circle meets no lattice line at a lattice site.  The q sector sits
+    in its vacuum; links and momenta zero."""
+    cx, cy, cz = center if center is not None else (nx / 2.0 - 0.5, ny / 2.0 - 0.5, nz / 2.0 - 0.5)
+    st = empty(nx, ny, nz)
+    z, y, x = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                          np.arange(nx, dtype=np.float64), indexing="ij")
+    rho = np.hypot(x - cx, y - cy)
+    th = np.arctan2(z - cz, rho - radius)
+    st[PHI], st[PHI + 1] = np.cos(th), np.sin(th)
+    st[PSI] = 1.0
+    return st

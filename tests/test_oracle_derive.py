@@ -6,6 +6,10 @@ what geometry and the paper fix, independently of how the record was summed:
   Sec. III.A with V = N_x N_y N_z h^3 follows;
 * the bound-state fractions f_total and f_p are ratios of those counted
   lengths (one bound and several free strings per sector);
+* a closed circular string is counted by its Manhattan length: Sigma|W| is
+  the number of faces the circle crosses, 2 per lattice line x = i or y = j it
+  cuts (about 8R, not 2 pi R), and L = h Sigma|W| (no length correction is
+  printed, so none is applied);
 * a relaxed static string at critical coupling has energy mu_lat per unit
   length, within the lattice's O(h^2) deficit of the BPS tension 2 pi sigma^2
   (Sec. IV), and with no motion the Lagrangian sums to minus the energy, so
@@ -123,3 +127,33 @@ def test_velocity_estimator_of_a_static_string():
     d = O.derive(m, _record(m, st))
     assert 0.0 <= d["v2_lag"] < 1e-6
     assert math.isnan(d["v2_pq"])
+
+
+@pytest.mark.parametrize("radius", [6.3, 9.7])
+def test_ring_length_is_the_counted_crossings(radius):
+    """A circular p-string of radius R in a z plane crosses each lattice line x = i with
+    |i - cx| < R twice and each line y = j likewise; each crossing pierces one face, so
+    Sigma|W_p| is that count exactly (about 8R: the Manhattan length of the circle, 4/pi of
+    its true length 2 pi R) and L_p = h Sigma|W_p|.  The fixture's phase is not periodic
+    in z: across the box's z boundary it winds the other way round the same circle, so
+    the periodic box holds the ring and an opposite copy half a box above it (a closed
+    string cannot carry net flux through the box), and Sigma|W_p| is twice one ring's."""
+    nx = ny = 32
+    nz = 8
+    m = O.model(nx, ny, nz)
+    st = I.ring(nx, ny, nz, radius)
+    cx = nx / 2.0 - 0.5
+    lines = sum(1 for i in range(nx) if abs(i - cx) < radius)
+    count = 2 * lines + 2 * lines                     # x and y lines (cy = cx), one ring
+    W = O.windings(m, st)
+    assert int(np.abs(W[0]).sum()) == int(np.abs(W[1]).sum()) == 2 * 2 * lines
+    assert np.abs(W[2]).sum() == 0                    # no face normal to z is pierced
+    assert np.abs(W[3:]).sum() == 0
+    # the ring in plane cz and its copy across the z boundary, face by face
+    cz = nz // 2 - 1
+    assert np.abs(W[:2, cz]).sum() == count and np.abs(W[:2, nz - 1]).sum() == count
+    d = O.derive(m, _record(m, st))
+    assert d["L_p"] == pytest.approx(m.h * 2 * count, rel=1e-15)
+    # the Manhattan length of the circle, against its true length
+    assert abs(count - 8 * radius) <= 4
+    assert count / (2 * math.pi * radius) == pytest.approx(4 / math.pi, rel=0.08)

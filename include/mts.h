@@ -229,7 +229,7 @@ int mts_segments(mts_ctx *ctx, double min_length, mts_segments_t *out, int64_t *
 /* Choose the update kernel.  ty in {4, 5, 8, 12} (and 13 in FP32) selects
  * the z-marching LDS-tiled kernel with tiles of 64 x ty sites and tz >= 1
  * planes per workgroup (default 8 x 32 in FP32, 4 x 32 in FP64; diagnostic
- * steps use at most 8 rows in FP32 and 4 in FP64, where their variant does
+ * steps use at most 8 rows in FP32 and 5 in FP64, where their variant does
  * not spill registers); every tile shape gives bitwise identical fields, and
  * records that agree to the rounding of their block sums.  ty = 0 selects the one-thread-per-site kernel, which computes
  * the plaquette sines directly and agrees with the tiled kernel to

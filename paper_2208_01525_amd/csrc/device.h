@@ -130,7 +130,43 @@ __device__ __forceinline__ T cos_t(T x) {
     return c;
 }
 
-__device__ __forceinline__ float atan2_t(float y, float x) { return atan2f(y, x); }
+// Two-argument arctangent in FP32, for the phases alpha = arg(phi) of the
+// winding stage: the octant reduction a = min(|x|, |y|) / max(|x|, |y|) in
+// [0, 1], atan(a) from an odd polynomial a q(a^2) of degree 15, then the
+// octant's reflections (pi/2 - r, pi - r, sign of y).  The coefficients are
+// a fit of atan on [0, 1] made for this function: Lawson's iteratively
+// reweighted least squares (minimax in the limit) on 4000 Chebyshev points,
+// rounded to FP32; evaluated in FP32 (Horner), atan(a) is within 1.4e-7 of
+// the true value on all of [0, 1], and the result within 4e-7 rad with the
+// reflections' rounding: far inside the 1e-4 rad margin the winding guard
+// keeps from the branch cut, so windings do not depend on it.  About 20
+// instructions against about 50 for the library's atan2f.  NaN for a NaN
+// argument; (0, 0) is the caller's case (phase_of).
+__device__ __forceinline__ float atan2_fast(float y, float x) {
+#pragma clang fp contract(fast)
+    constexpr float C0 = 0.9999993443489075f, C1 = -0.33329859375953674f, C2 = 0.19946566224098206f,
+                    C3 = -0.1390862911939621f, C4 = 0.09642194956541061f, C5 = -0.05591228976845741f,
+                    C6 = 0.021862929686903954f, C7 = -0.004054558929055929f;
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    const float a = mn * __builtin_amdgcn_rcpf(mx);
+    const float s = a * a;
+    float q = C7;
+    q = q * s + C6;
+    q = q * s + C5;
+    q = q * s + C4;
+    q = q * s + C3;
+    q = q * s + C2;
+    q = q * s + C1;
+    q = q * s + C0;
+    float r = a * q;
+    if (ay > ax) r = 1.57079637f - r;
+    if (x < 0.0f) r = 3.14159274f - r;
+    r = copysignf(r, y);
+    return (x != x || y != y) ? x + y : r;
+}
+
+__device__ __forceinline__ float atan2_t(float y, float x) { return atan2_fast(y, x); }
 __device__ __forceinline__ double atan2_t(double y, double x) { return atan2(y, x); }
 __device__ __forceinline__ float rint_t(float x) { return rintf(x); }
 __device__ __forceinline__ double rint_t(double x) { return rint(x); }

@@ -679,11 +679,11 @@ static hipError_t launch_ty(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> 
         // ahead: at the row counts they run with it costs no occupancy and
         // saves about 5 % (512^3: 4.82 against 5.08 ms).  The FP64 variant
         // is at its register limit already.  Diagnostic steps run at most 8
-        // rows in FP32 and 4 in FP64, so the shapes only plain steps use have
+        // rows in FP32 and 5 in FP64, so the shapes only plain steps use have
         // no diagnostic variant.  With wabs the windings and the Gauss
         // residual are fused in (FP32; momenta out of place).
         constexpr int DPF = sizeof(T) == 4 ? 1 : 0;
-        if constexpr (TY == 13 || (TY != 4 && sizeof(T) == 8)) {
+        if constexpr (TY == 13 || (TY > 5 && sizeof(T) == 8)) {
             return hipErrorNotSupported;
         } else {
             if (wabs) {
@@ -757,7 +757,7 @@ hipError_t launch_step_tile_batch(const BatchBox<T> *boxes_dev, int nbox, uint32
 #define MTS_BATCH_CASE(TYV)                                           \
     case TYV:                                                         \
         if (diag) {                                                   \
-            if constexpr (TYV == 13 || (TYV != 4 && sizeof(T) == 8)) {  \
+            if constexpr (TYV == 13 || (TYV > 5 && sizeof(T) == 8)) {   \
                 return hipErrorNotSupported;                          \
             } else {                                                  \
                 if (nt) MTS_BATCH_LAUNCH(TYV, true, true, false);     \

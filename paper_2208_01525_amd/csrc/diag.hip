@@ -147,20 +147,19 @@ hipError_t launch_wind_gauss(const Geom &g, Fields<T> f, Moms<T> mom, const T *a
 
 // ---------------------------------------------------------------- fix-up of the fused windings
 
-uint32_t wind_fix_blocks(const Geom &g) {
-    return ((g.nxy * (uint32_t)g.nz + FIX_SITES - 1) / FIX_SITES + 255) / 256;
-}
+uint32_t wind_fix_blocks(const Geom &g) { return fix_blocks_of(g.nxy * (uint32_t)g.nz); }
 
 // The fused diagnostic step marks (WABS_FIX) the sites whose windings used a
 // link the guard sends to FP64; here each marked site's three faces are
 // evaluated as the post-step kernel does, its byte rewritten and its sum |W|
 // added to the SL_FIX_P / SL_FIX_Q partials (the fused kernel counted nothing
-// for it).  A thread scans 16 sites per sector with one 16-byte load (the
-// sector's byte plane is padded to a multiple of 64 sites).
+// for it).  A thread scans 16 sites per sector and pass with one 16-byte
+// load (the sector's byte plane is padded to a multiple of 64 sites); at
+// most FIX_MAX_BLOCKS blocks, each looping over its chunks of the box.
 template <typename T>
 __global__ __launch_bounds__(256) void wind_fix_kernel(Geom g, Fields<T> f, T h, uint8_t *wabs, uint32_t plane,
                                                        Partials part) {
-    fix_block(g, f, h, wabs, plane, part, blockIdx.x, threadIdx.x);
+    fix_block(g, f, h, wabs, plane, part, blockIdx.x, gridDim.x, threadIdx.x);
 }
 
 template <typename T>
@@ -193,7 +192,9 @@ uint32_t overlap_words(const Geom &g) { return (uint32_t)(g.nx / 64) * (uint32_t
 // less.
 __global__ __launch_bounds__(256) void cells_kernel(Geom g, const uint8_t *wabs, uint8_t *cells, uint64_t *bits,
                                                     uint32_t plane, uint32_t nwords) {
-    cells_block(g, wabs, cells, bits, plane, nwords, xcd_order(blockIdx.x, gridDim.x), threadIdx.x, threadIdx.y);
+    const uint32_t blk = xcd_order(blockIdx.x, gridDim.x);
+    if (cells_by_words(g)) cells4_block(g, wabs, cells, bits, plane, nwords, blk, threadIdx.x, threadIdx.y);
+    else cells_block(g, wabs, cells, bits, plane, nwords, blk, threadIdx.x, threadIdx.y);
 }
 
 hipError_t launch_cells(const Geom &g, const uint8_t *wabs, uint8_t *cells, uint64_t *bits, uint32_t plane,
@@ -281,7 +282,7 @@ __global__ __launch_bounds__(256) void fix_batch_kernel(const BatchPost<T> *boxe
     const int k = box_of(boxes, nbox, blockIdx.x, &BatchPost<T>::blk_fix);
     const BatchPost<T> &b = boxes[k];
     fix_block(b.g, fields_global(b.f[parity]), b.h, as_global(b.wabs), b.plane, part_global(b.part),
-              blockIdx.x - b.blk_fix, threadIdx.x);
+              blockIdx.x - b.blk_fix, fix_blocks_of(b.g.nxy * (uint32_t)b.g.nz), threadIdx.x);
 }
 
 template <typename T>
@@ -289,8 +290,12 @@ __global__ __launch_bounds__(256) void cells_batch_kernel(const BatchPost<T> *bo
     const uint32_t t = xcd_order(blockIdx.x, total);
     const int k = box_of(boxes, nbox, t, &BatchPost<T>::blk_cells);
     const BatchPost<T> &b = boxes[k];
-    cells_block(b.g, as_global(b.wabs), as_global(b.cells), b.bits ? as_global(b.bits) : nullptr, b.plane, b.nwords,
-                t - b.blk_cells, threadIdx.x & 63, threadIdx.x >> 6);
+    if (cells_by_words(b.g))
+        cells4_block(b.g, as_global(b.wabs), as_global(b.cells), b.bits ? as_global(b.bits) : nullptr, b.plane,
+                     b.nwords, t - b.blk_cells, threadIdx.x & 63, threadIdx.x >> 6);
+    else
+        cells_block(b.g, as_global(b.wabs), as_global(b.cells), b.bits ? as_global(b.bits) : nullptr, b.plane,
+                    b.nwords, t - b.blk_cells, threadIdx.x & 63, threadIdx.x >> 6);
 }
 
 template <typename T>
@@ -313,7 +318,8 @@ __global__ __launch_bounds__(1024) void reduce_batch_kernel(const BatchPost<T> *
 }
 
 uint32_t cells_blocks(const Geom &g) {
-    return (uint32_t)((g.nx + 63) / 64) * (uint32_t)((g.ny + 3) / 4) * (uint32_t)((g.nz + CZ - 1) / CZ);
+    const uint32_t gx = cells_by_words(g) ? (uint32_t)g.nx / 256 : (uint32_t)((g.nx + 63) / 64);
+    return gx * (uint32_t)((g.ny + 3) / 4) * (uint32_t)((g.nz + CZ - 1) / CZ);
 }
 
 template <typename T>

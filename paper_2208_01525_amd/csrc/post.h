@@ -85,17 +85,33 @@ __device__ __forceinline__ void group_sum_store(double (&v)[NV], Partials part, 
     __syncthreads();
 }
 
-constexpr int FIX_SITES = 16;   // sites per thread of the fix-up scan (one 16-byte load per sector)
+constexpr int FIX_SITES = 16;   // sites per thread and pass of the fix-up scan (one 16-byte load per sector)
+constexpr uint32_t FIX_CHUNK = 256 * FIX_SITES;   // sites per (virtual) block and pass
+constexpr uint32_t FIX_MAX_BLOCKS = 1024;
 
+// Blocks of the fix-up scan of a box of S sites: one pass each up to
+// FIX_MAX_BLOCKS, then several passes per block.  Nearly every byte it reads
+// is unmarked, so the scan is a stream of 16-byte loads; few blocks that
+// loop keep it near the bandwidth of that stream, where one short-lived
+// block per 4096 sites spent most of its time starting and reducing.
+__host__ __device__ inline uint32_t fix_blocks_of(uint32_t S) {
+    const uint32_t chunks = (S + FIX_CHUNK - 1) / FIX_CHUNK;
+    return chunks < FIX_MAX_BLOCKS ? chunks : FIX_MAX_BLOCKS;
+}
 
+// Virtual block lblk of nblk scans the chunks lblk, lblk + nblk, ... of the
+// box; every marked site's three faces are evaluated in FP64 where the guard
+// asks for it (face_windings), its byte rewritten and |W| summed (integers:
+// the partials do not depend on how the chunks are dealt).
 template <typename T>
 __device__ __forceinline__ void fix_block(const Geom &g, const Fields<T> &f, T h, uint8_t *wabs, uint32_t plane,
-                                          Partials part, uint32_t lblk, uint32_t tid, int group = 0,
+                                          Partials part, uint32_t lblk, uint32_t nblk, uint32_t tid, int group = 0,
                                           bool valid = true) {
     const uint32_t S = g.nxy * (uint32_t)g.nz;
-    const uint32_t s0 = (lblk * 256 + tid) * FIX_SITES;
     double acc[2] = {0, 0};
-    if (valid && s0 < S) {
+    for (uint32_t c = lblk; valid && c * FIX_CHUNK < S; c += nblk) {
+        const uint32_t s0 = c * FIX_CHUNK + tid * FIX_SITES;
+        if (s0 >= S) continue;
 #pragma unroll
         for (int sec = 0; sec < 2; sec++) {
             uint8_t *wb = wabs + (size_t)sec * plane + s0;
@@ -171,6 +187,77 @@ __device__ __forceinline__ void cells_block(const Geom &g, const uint8_t *wabs, 
     }
 }
 
+
+// Rows whose width is a multiple of 256 take four cells per lane: a block of
+// 64 x 4 lanes covers 256 x 4 columns and walks CZ planes, reading the
+// packed |W| bytes as 32-bit words and adding the six face fields of four
+// cells at once (each field is at most 3, so no byte of the sum carries into
+// the next).  The x neighbour of a lane's last cell is the next lane's first
+// byte (a shuffle; the row's last lane reads it).  With bits, lane k < 4
+// assembles the 64-cell word k of the wave's 256 cells from four ballots.
+__host__ __device__ inline bool cells_by_words(const Geom &g) { return g.nx % 256 == 0; }
+
+__device__ __forceinline__ uint64_t spread4(uint32_t v) {   // bit i of v (16 bits) to bit 4 i
+    uint64_t x = v & 0xFFFFu;
+    x = (x | (x << 24)) & 0x000000FF000000FFull;
+    x = (x | (x << 12)) & 0x000F000F000F000Full;
+    x = (x | (x << 6)) & 0x0303030303030303ull;
+    x = (x | (x << 3)) & 0x1111111111111111ull;
+    return x;
+}
+
+__device__ __forceinline__ void cells4_block(const Geom &g, const uint8_t *wabs, uint8_t *cells, uint64_t *bits,
+                                             uint32_t plane, uint32_t nwords, uint32_t blk, int lane, int ty) {
+    const uint32_t gx = (uint32_t)g.nx / 256, gy = (g.ny + 3) / 4;
+    const uint32_t bx = blk % gx, by = (blk / gx) % gy, bz = blk / (gx * gy);
+    const int x = (int)bx * 256 + 4 * lane;
+    const int y = by * 4 + ty;
+    const bool in = y < g.ny;     // uniform per wave
+    if (!in) return;              // no barrier below: the wave may leave
+    const int z0 = bz * CZ, z1 = min(z0 + CZ, g.nz);
+    const uint32_t col = (uint32_t)x + (uint32_t)g.nx * (uint32_t)y;
+    const uint32_t colx4 = (uint32_t)wrap1(x + 4, g.nx) + (uint32_t)g.nx * (uint32_t)y;   // last lane only
+    const uint32_t coly = (uint32_t)x + (uint32_t)g.nx * (uint32_t)wrap1(y + 1, g.ny);
+    constexpr uint32_t M = 0x03030303u;
+    uint32_t w0[2];
+#pragma unroll
+    for (int sec = 0; sec < 2; sec++)
+        w0[sec] = *reinterpret_cast<const uint32_t *>(wabs + (size_t)sec * plane + col + g.nxy * (uint32_t)z0);
+    for (int z = z0; z < z1; z++) {
+        const uint32_t off = g.nxy * (uint32_t)z, offz = g.nxy * (uint32_t)wrap1(z + 1, g.nz);
+        uint32_t n[2];
+#pragma unroll
+        for (int sec = 0; sec < 2; sec++) {
+            const uint8_t *w = wabs + (size_t)sec * plane;
+            const uint32_t o = w0[sec];
+            const uint32_t wz = *reinterpret_cast<const uint32_t *>(w + col + offz);
+            const uint32_t wy = *reinterpret_cast<const uint32_t *>(w + coly + off);
+            uint32_t nb = (uint32_t)__shfl_down((int)o, 1, 64) & 0xFFu;   // next lane's first cell
+            if (lane == 63) nb = w[colx4 + off];
+            const uint32_t wx = (o >> 8) | (nb << 24);
+            n[sec] = (o & M) + (wx & M) + ((o >> 2) & M) + ((wy >> 2) & M) + ((o >> 4) & M) + ((wz >> 4) & M);
+            *reinterpret_cast<uint32_t *>(cells + (size_t)sec * plane + col + off) = n[sec];
+            w0[sec] = wz;
+        }
+        if (bits) {
+#pragma unroll
+            for (int sec = 0; sec < 2; sec++) {
+                const uint32_t v = n[sec];
+                uint64_t word = 0;
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const uint64_t b = __ballot(((v >> (8 * j)) & 0xFFu) != 0);
+                    word |= spread4((uint32_t)(b >> (16 * (lane & 3)))) << j;
+                }
+                if (lane < 4) {
+                    const uint32_t xw = bx * 4 + (uint32_t)lane;   // word index within the row
+                    const uint32_t wi = xw + (uint32_t)(g.nx / 64) * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
+                    bits[(size_t)sec * nwords + wi] = word;
+                }
+            }
+        }
+    }
+}
 
 // x-dilation of the word at (xw, y, z) by one cell with periodic wrap
 __device__ __forceinline__ uint64_t dilate_x(const uint64_t *m, uint32_t row, int xw, int nw) {

@@ -158,9 +158,9 @@ def test_batch_fused_matches_box_by_box():
     post-step kernels box by box: fields bitwise, windings, overlap and cells bitwise, sums
     to rounding.  Box widths 64 and 128 take the packed-word overlap, the others the byte
     one; guard cases are planted in one box."""
-    shapes = [(64, 9, 6), (24, 16, 12), (70, 9, 5), (128, 4, 4), (33, 20, 7)]
-    eras = [0.5, 2.0 / 3.0, 0.5, 2.0 / 3.0, 0.5]
-    s_b = [0.0, 1.0, 1.0, 0.0, 1.0]
+    shapes = [(64, 9, 6), (24, 16, 12), (70, 9, 5), (128, 4, 4), (33, 20, 7), (256, 5, 6)]
+    eras = [0.5, 2.0 / 3.0, 0.5, 2.0 / 3.0, 0.5, 2.0 / 3.0]
+    s_b = [0.0, 1.0, 1.0, 0.0, 1.0, 0.0]
     kw = dict(precision="fp32", diag_every=2)
     states = [I.to_f32_values(I.random_full(*sh, 50 + k, link=0.7, mom=0.4)) for k, sh in enumerate(shapes)]
     states[0] = _planted(*shapes[0], 41)
@@ -169,7 +169,7 @@ def test_batch_fused_matches_box_by_box():
         bt = P.Batch([P.make_params(*sh, eta_ref=5.0 + k, **kw) for k, sh in enumerate(shapes)])
         bt.set_fused_diagnostics(rows)
         assert bt.get_fused_diagnostics() == rows
-        bt.set_tile(8, [4, 3, 5, 2, 7])
+        bt.set_tile(8, [4, 3, 5, 2, 7, 3])
         for k, st in enumerate(states):
             bt.set_fields(k, st)
         bt.step(5, [1.0] * len(shapes), eras, s_b)
@@ -186,3 +186,33 @@ def test_batch_fused_matches_box_by_box():
             for s in range(2):
                 assert a["gauss_abs"][s] == pytest.approx(b["gauss_abs"][s], rel=1e-11, abs=1e-12)
                 assert a["gauss_scale"][s] == pytest.approx(b["gauss_scale"][s], rel=1e-11)
+
+
+@pytest.mark.parametrize("precision,rows", [("fp32", 8), ("fp32", 0), ("fp64", 0)])
+@pytest.mark.parametrize("geom", [(256, 6, 5), (512, 5, 18)])
+def test_cells_of_wide_rows_match_oracle(geom, precision, rows):
+    """Rows whose width is a multiple of 256 take the cells kernel that reads the packed |W|
+    bytes as words, four cells per lane, and assembles the occupancy words from ballots:
+    cells equal the oracle's cells of the same windings (clipped to 3 per face, what a packed
+    byte holds) and the overlap count the oracle's, on random fields with many windings
+    (ragged y and z blocks; the second box crosses two 16-plane blocks)."""
+    nx, ny, nz = geom
+    st = I.random_full(nx, ny, nz, 61, link=0.7, mom=0.4)
+    if precision == "fp32":
+        st = I.to_f32_values(st)
+    m = O.model(nx, ny, nz, eta_ref=9.0, kappa=0.9)
+    W = O.windings(m, st)
+    assert np.abs(W).sum() > 100
+    ref_cells = O.cells(m, np.clip(W, -3, 3))
+    lat = P.Lattice(P.make_params(nx, ny, nz, precision=precision, eta_ref=9.0, diag_every=1, kappa=0.9),
+                    device="cuda:0")
+    if precision == "fp32":
+        lat.set_fused_diagnostics(rows)
+    lat.set_fields(st)
+    lat.step(1, 3.0, 0.5, 1.0)
+    rec = lat.diagnostics()[0]
+    got = lat.get_cells().astype(np.int32)
+    lat.close()
+    assert np.array_equal(got, ref_cells)
+    assert rec["wind_abs"] == (int(np.abs(W[:3]).sum()), int(np.abs(W[3:]).sum()))
+    assert rec["pq_count2"] == sum(O.overlap(m, O.cells(m, W)))

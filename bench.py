@@ -67,7 +67,7 @@ def measured_traffic(n, precision, tile, nt, pf, pp=False, xcd=True):
 
 
 def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0.5, s=1.0, eta_ref=128.0, seed=1,
-            tile=None, time_blocking=None):
+            tile=None, time_blocking=None, tune_cache=None):
     params = P.make_params(n, precision=precision, eta_ref=eta_ref, diag_every=diag_every)
     lat = P.Lattice(params, device="cuda:0")
     tuned = None
@@ -82,7 +82,7 @@ def run_box(P, torch, n, precision, warmup, steps, diag_every, eta0=1.0, era_m=0
         if len(tile) > 5:
             lat.set_tile_order(bool(tile[5]))
     else:
-        tuned = lat.autotune(4)      # times every tile shape on this machine (leaves seed-0 fields)
+        tuned = lat.autotune(4, cache=tune_cache)   # times every tile shape on this machine (unless cached)
     if time_blocking is not None:
         lat.set_time_blocking(*time_blocking)
     ceiling = lat.bandwidth_probe(5)  # this box's copy rate and the update pattern's rate (overwrites)
@@ -286,6 +286,8 @@ def main():
                     help="comma list of extra legs: 1024 (1024^3 matter era, s=0, FP32 then FP64, no diagnostics) "
                          "and/or 1280 (1280^3 radiation era, s=1, FP32, diagnostics every 50)")
     ap.add_argument("--leg-steps", type=int, default=20)
+    ap.add_argument("--autotune-cache", type=str, default=None,
+                    help="file of stored autotuner choices (mts_autotune_cached); default: tune afresh")
     args = ap.parse_args()
     if args.source_hash:
         print(kernel_source_hash())
@@ -305,10 +307,12 @@ def main():
 
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
     tblock = tuple(int(v) for v in args.time_blocking.split(",")) if args.time_blocking else None
-    fp32 = run_box(P, torch, args.n, "fp32", args.warmup, args.steps, diag_every=10, tile=tile, time_blocking=tblock)
+    fp32 = run_box(P, torch, args.n, "fp32", args.warmup, args.steps, diag_every=10, tile=tile, time_blocking=tblock,
+                   tune_cache=args.autotune_cache)
     print(f"fp32: {fp32['value']:.4g} site-updates/s, kernel {fp32['kernel_ms']:.3f} ms, "
           f"{fp32['roofline']['frac']:.3f} of HBM peak", file=sys.stderr, flush=True)
-    fp64 = run_box(P, torch, args.n, "fp64", args.warmup, args.fp64_steps, diag_every=10) if args.fp64_steps else None
+    fp64 = (run_box(P, torch, args.n, "fp64", args.warmup, args.fp64_steps, diag_every=10,
+                    tune_cache=args.autotune_cache) if args.fp64_steps else None)
     if fp64:
         print(f"fp64: {fp64['value']:.4g} site-updates/s, kernel {fp64['kernel_ms']:.3f} ms, "
               f"{fp64['roofline']['frac']:.3f} of HBM peak", file=sys.stderr, flush=True)
@@ -324,13 +328,14 @@ def main():
             wl = "1024^3, matter era (m=2/3), s=0, a=1 at eta=256, no diagnostics"
             for prec in ("fp32", "fp64"):
                 r = run_box(P, torch, 1024, prec, 5, args.leg_steps, diag_every=0, era_m=2.0 / 3.0, s=0.0,
-                            eta_ref=256.0)
+                            eta_ref=256.0, tune_cache=args.autotune_cache)
                 legs[f"1024_{prec}"] = leg_summary(r, prec, 1024, args.leg_steps, wl)
                 print(f"leg 1024 {prec}: kernel {r['kernel_ms']:.2f} ms, {r['roofline']['frac']:.3f} of HBM peak",
                       file=sys.stderr, flush=True)
         elif leg == "1280":
             wl = "1280^3, radiation era (m=1/2), s=1, a=1 at eta=201, diagnostics every 50"
-            r = run_box(P, torch, 1280, "fp32", 5, args.leg_steps, diag_every=50, eta_ref=201.0)
+            r = run_box(P, torch, 1280, "fp32", 5, args.leg_steps, diag_every=50, eta_ref=201.0,
+                        tune_cache=args.autotune_cache)
             legs["1280_fp32"] = leg_summary(r, "fp32", 1280, args.leg_steps, wl)
             print(f"leg 1280 fp32: kernel {r['kernel_ms']:.2f} ms, {r['roofline']['frac']:.3f} of HBM peak",
                   file=sys.stderr, flush=True)

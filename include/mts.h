@@ -320,6 +320,21 @@ int mts_get_time_blocking(const mts_ctx *ctx, int32_t *steps, int32_t *ty, int32
  * mts_init_fields / mts_set_fields. */
 int mts_autotune(mts_ctx *ctx, int32_t steps, int32_t *ty, int32_t *tz, double *ms_per_step);
 
+/* mts_autotune through a cache file (a tuning aid, no part of the method):
+ * the key is the GPU's architecture name, its compute-unit count, the box
+ * dimensions and the precision.  If cache_path (a text file the caller
+ * owns; one line per tuned key, appended) holds the key, its stored choice
+ * (tile shape, store mode, load pipeline, momentum ping-pong, tile order,
+ * steps per sweep) is applied with the setters, nothing is timed and the
+ * fields are left alone: *hit = 1, *ms_per_step = the stored time.
+ * Otherwise mts_autotune runs (overwriting the fields) and its choice is
+ * appended: *hit = 0, or -1 if the file could not be written (the choice is
+ * applied; mts_last_error says why).  A stored choice the context cannot
+ * take (no room for a second momentum copy) is tuned afresh.  MTS_EINVAL
+ * for a NULL path.  hit, ty, tz and ms_per_step may be NULL. */
+int mts_autotune_cached(mts_ctx *ctx, int32_t steps, const char *cache_path, int32_t *hit, int32_t *ty, int32_t *tz,
+                        double *ms_per_step);
+
 /* Bandwidth probe (a measurement aid, not part of the method): on this
  * context's state buffer, time `reps` launches each of (a) a plain device
  * copy of one field copy onto the other, one float4 per thread, and (b) a

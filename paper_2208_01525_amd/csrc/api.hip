@@ -1214,6 +1214,107 @@ int mts_autotune(mts_ctx *c, int32_t steps, int32_t *ty_out, int32_t *tz_out, do
     return MTS_OK;
 }
 
+}  // extern "C"
+
+// ---- autotune cache
+//
+// One line per tuned configuration, appended after a tuning run:
+//   mts-tune-1 <arch> cu=<CUs> n=<nx>x<ny>x<nz> prec=<fp32|fp64> | ty= tz= nt= pf= pp= xcd= tb= ty2= tz2= ms=
+// The last line with a matching key wins; lines that do not parse are skipped.
+
+namespace {
+
+std::string tune_key(const mts_ctx *c) {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    int cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        cus = prop.multiProcessorCount;
+    }
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "mts-tune-1 %s cu=%d n=%dx%dx%d prec=%s", arch.c_str(), cus, c->p.nx, c->p.ny,
+                  c->p.nz, c->p.precision == MTS_FP64 ? "fp64" : "fp32");
+    return buf;
+}
+
+struct TunePick {
+    int ty, tz, nt, pf, pp, xcd, tb, ty2, tz2;
+    double ms;
+};
+
+bool tune_lookup(const char *path, const std::string &key, TunePick *out) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+        const char *bar = std::strstr(line, " | ");
+        if (!bar || (size_t)(bar - line) != key.size() || std::strncmp(line, key.c_str(), key.size()) != 0) continue;
+        TunePick t{};
+        if (std::sscanf(bar + 3, "ty=%d tz=%d nt=%d pf=%d pp=%d xcd=%d tb=%d ty2=%d tz2=%d ms=%lf", &t.ty, &t.tz,
+                        &t.nt, &t.pf, &t.pp, &t.xcd, &t.tb, &t.ty2, &t.tz2, &t.ms) == 10) {
+            *out = t;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+bool tune_store(const char *path, const std::string &key, const TunePick &t) {
+    FILE *f = std::fopen(path, "a");
+    if (!f) return false;
+    const int w = std::fprintf(f, "%s | ty=%d tz=%d nt=%d pf=%d pp=%d xcd=%d tb=%d ty2=%d tz2=%d ms=%.6f\n", key.c_str(),
+                               t.ty, t.tz, t.nt, t.pf, t.pp, t.xcd, t.tb, t.ty2, t.tz2, t.ms);
+    return std::fclose(f) == 0 && w > 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mts_autotune_cached(mts_ctx *c, int32_t steps, const char *cache_path, int32_t *hit, int32_t *ty_out,
+                        int32_t *tz_out, double *ms_out) {
+    if (!c || steps < 1 || !cache_path) return MTS_EINVAL;
+    const std::string key = tune_key(c);
+    TunePick t{};
+    if (tune_lookup(cache_path, key, &t)) {
+        // apply the stored choice with the setters (each checks its own values)
+        int rc = mts_set_tile(c, t.ty, t.tz);
+        if (rc == MTS_OK) rc = mts_set_streaming_stores(c, t.nt);
+        if (rc == MTS_OK) rc = mts_set_prefetch(c, t.pf);
+        if (rc == MTS_OK) rc = mts_set_tile_order(c, t.xcd);
+        if (rc == MTS_OK) rc = mts_set_momentum_pingpong(c, t.pp);
+        if (rc == MTS_OK) rc = mts_set_time_blocking(c, t.tb, t.ty2, t.tz2);
+        if (rc == MTS_OK) {
+            if (hit) *hit = 1;
+            if (ty_out) *ty_out = t.ty;
+            if (tz_out) *tz_out = t.tz;
+            if (ms_out) *ms_out = t.ms;
+            return MTS_OK;
+        }
+        if (rc != MTS_ENOMEM && rc != MTS_EINVAL) return rc;
+        // a choice this context cannot take (no room for a second momentum
+        // copy, a shape this build no longer has): tune afresh
+        c->err.clear();
+    }
+    double ms = 0.0;
+    int32_t ty = 0, tz = 0;
+    const int rc = mts_autotune(c, steps, &ty, &tz, &ms);
+    if (rc != MTS_OK) return rc;
+    t = TunePick{c->tile.ty, c->tile.tz, c->nt ? 1 : 0, c->pf ? 1 : 0, c->mpp ? 1 : 0, c->xcd ? 1 : 0, c->tblock,
+                 c->tile2.ty, c->tile2.tz, ms};
+    const bool stored = tune_store(cache_path, key, t);
+    if (!stored) c->err = std::string("autotune cache: could not append to ") + cache_path;
+    if (hit) *hit = stored ? 0 : -1;
+    if (ty_out) *ty_out = ty;
+    if (tz_out) *tz_out = tz;
+    if (ms_out) *ms_out = ms;
+    return MTS_OK;
+}
+
 int mts_timing_enable(mts_ctx *c, int32_t on) {
     if (!c) return MTS_EINVAL;
     c->timing = on != 0;

@@ -21,7 +21,7 @@ MTS_FP32, MTS_FP64 = 1, 2
 NOALLOC_MAX_SITES = 8192        # MTS_NOALLOC_MAX_SITES of include/mts.h
 
 EXPORTS = ("mts_state_bytes", "mts_create", "mts_destroy", "mts_init_fields", "mts_step", "mts_cool", "mts_diagnostics",
-           "mts_get_fields", "mts_set_fields", "mts_get_windings", "mts_get_cells", "mts_get_sites", "mts_get_sites_noalloc", "mts_segments", "mts_set_tile", "mts_get_tile", "mts_set_streaming_stores", "mts_bandwidth_probe", "mts_get_streaming_stores", "mts_autotune", "mts_timing_enable",
+           "mts_get_fields", "mts_set_fields", "mts_get_windings", "mts_get_cells", "mts_get_sites", "mts_get_sites_noalloc", "mts_segments", "mts_set_tile", "mts_get_tile", "mts_set_streaming_stores", "mts_bandwidth_probe", "mts_get_streaming_stores", "mts_autotune", "mts_autotune_cached", "mts_timing_enable",
            "mts_timing_read", "mts_set_time_blocking", "mts_get_time_blocking", "mts_set_prefetch", "mts_get_prefetch", "mts_set_fused_diagnostics", "mts_get_fused_diagnostics", "mts_set_momentum_pingpong", "mts_get_momentum_pingpong", "mts_set_tile_order", "mts_get_tile_order", "mts_last_error", "mts_strerror",
            "mts_batch_state_bytes", "mts_batch_create", "mts_batch_destroy", "mts_batch_size",
            "mts_batch_init_fields", "mts_batch_step", "mts_batch_diagnostics", "mts_batch_get_fields",
@@ -130,6 +130,8 @@ def load():
     L.mts_get_tile.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     i32p = ctypes.POINTER(ctypes.c_int32)
     L.mts_autotune.argtypes = [vp, ctypes.c_int32, i32p, i32p, ctypes.POINTER(ctypes.c_double)]
+    L.mts_autotune_cached.argtypes = [vp, ctypes.c_int32, ctypes.c_char_p, i32p, i32p, i32p,
+                                      ctypes.POINTER(ctypes.c_double)]
     L.mts_batch_autotune.argtypes = [vp, ctypes.c_int32, i32p, i32p, ctypes.POINTER(ctypes.c_double)]
     L.mts_timing_enable.argtypes = [vp, ctypes.c_int32]
     i64p, dp = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
@@ -324,9 +326,17 @@ class Lattice:
         self._check(self.L.mts_get_tile(self.ctx, ctypes.byref(ty), ctypes.byref(tz)))
         return ty.value, tz.value
 
-    def autotune(self, steps=5):
+    def autotune(self, steps=5, cache=None):
+        """(ty, tz, ms per step); with `cache` (a file path) through mts_autotune_cached, whose
+        hit flag is then in `self.autotune_hit`."""
         ty, tz, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
-        self._check(self.L.mts_autotune(self.ctx, int(steps), ctypes.byref(ty), ctypes.byref(tz), ctypes.byref(ms)))
+        if cache is None:
+            self._check(self.L.mts_autotune(self.ctx, int(steps), ctypes.byref(ty), ctypes.byref(tz), ctypes.byref(ms)))
+        else:
+            hit = ctypes.c_int32()
+            self._check(self.L.mts_autotune_cached(self.ctx, int(steps), str(cache).encode(), ctypes.byref(hit),
+                                                   ctypes.byref(ty), ctypes.byref(tz), ctypes.byref(ms)))
+            self.autotune_hit = hit.value
         return ty.value, tz.value, ms.value
 
     def timing_enable(self, on=True):

@@ -116,6 +116,8 @@ def test_null_context_rejected():
     cnt = ctypes.c_int32()
     assert L.mts_diagnostics(None, None, 0, ctypes.byref(cnt)) == M.MTS_EINVAL
     assert L.mts_strerror(M.MTS_EUNSTABLE) == b"MTS_EUNSTABLE"
+    assert L.mts_autotune_cached(None, 3, b"/nonexistent/cache", None, None, None, None) == M.MTS_EINVAL
+    assert L.mts_batch_set_persistent(None, 1, 0.0) == M.MTS_EINVAL
 
 
 def test_noalloc_limit_matches_header_and_null_context_rejected():

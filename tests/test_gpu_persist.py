@@ -107,3 +107,32 @@ def test_persistent_wait_limit_reports_ehip():
     ref, _ = _run("fp32", False, 4, 2, n=12, diag_every=0, states=states)
     for k in range(len(SHAPES)):
         assert np.array_equal(got[k], ref[k]), k
+
+
+def test_autotune_cache_hit_applies_the_stored_choice(tmp_path):
+    """mts_autotune_cached: a miss tunes and appends one line for the key (arch, CU count,
+    box, precision); a second context of the same box hits it, takes the same settings
+    without timing anything and leaves its fields alone; unparsable lines are skipped."""
+    print("autotune cache", flush=True)
+    cache = tmp_path / "tune.txt"
+    cache.write_text("not a cache line\n")
+    geom = (96, 20, 24)
+    a = P.Lattice(P.make_params(*geom, precision="fp32", eta_ref=6.0), device="cuda:0")
+    a.autotune(1, cache=cache)
+    assert a.autotune_hit == 0
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 2 and lines[1].startswith("mts-tune-1 ") and "n=96x20x24 prec=fp32 | ty=" in lines[1]
+    want = (a.get_tile(), a.get_streaming_stores(), a.get_prefetch(), a.get_momentum_pingpong(),
+            a.get_tile_order(), a.get_time_blocking())
+    a.close()
+    st = I.to_f32_values(I.random_full(*geom, 5, link=0.5, mom=0.3))
+    b = P.Lattice(P.make_params(*geom, precision="fp32", eta_ref=6.0), device="cuda:0")
+    b.set_fields(st)
+    b.autotune(1, cache=cache)
+    assert b.autotune_hit == 1
+    got = (b.get_tile(), b.get_streaming_stores(), b.get_prefetch(), b.get_momentum_pingpong(),
+           b.get_tile_order(), b.get_time_blocking())
+    assert got == want
+    assert np.array_equal(b.get_fields(), st)
+    b.close()
+    assert len(cache.read_text().splitlines()) == 2

@@ -60,14 +60,14 @@ def asymptotic(records, eta_lo, eta_hi):
 
 
 def run(n, era_m, seed, m_damp=0.9, dx=0.5, dt=0.1, diag_every=10, eta_lo=230.0, eta_end=None,
-        device="cuda:0", chunk=200, log=sys.stderr):
+        device="cuda:0", chunk=200, log=sys.stderr, tune_cache=None):
     """One validation run; returns (records, asymptotic values).  Progress lines go to
     `log` (None: silent)."""
     eta_end = eta_end if eta_end is not None else n * dx / 2.0
     params = M.make_params(n, eta_ref=eta_end, diag_every=diag_every, dx=dx, dt=dt)
     lat = M.Lattice(params, device=device)
     try:
-        lat.autotune(2)
+        lat.autotune(2, cache=tune_cache)
         lat.init_fields(seed)
         t0 = time.perf_counter()
         lat.cool(int(round(11.0 * 30.0)), 1.0 / 30.0)
@@ -93,6 +93,7 @@ def run(n, era_m, seed, m_damp=0.9, dx=0.5, dt=0.1, diag_every=10, eta_lo=230.0,
 
 SUMMARY_KEYS = ("v2_lag", "v2_pq", "xi_W_dot", "xi_p_dot", "xi_pq_dot", "xi_lag_dot", "f_total", "f_p")
 MANHATTAN = math.sqrt(1.5)   # xi under L -> (2/3) L
+WINDING_SLOPES = ("xi_W_dot", "xi_p_dot", "xi_q_dot", "xi_pq_dot")
 
 
 def summarize(per_seed):
@@ -132,7 +133,9 @@ def table(groups):
             if key not in sm:
                 continue
             m, sd = sm[key]
-            alt = f"{m * MANHATTAN:.4g} ± {sd * MANHATTAN:.2g}" if key.startswith("xi_") else ""
+            # the reading changes only the separations taken from the winding length (xi_L comes
+            # from the Lagrangian and the tension, not from a counted length)
+            alt = f"{m * MANHATTAN:.4g} ± {sd * MANHATTAN:.2g}" if key in WINDING_SLOPES else ""
             rows.append(f"| {n} | {name} ({sm['seeds']} seeds) | {key} | {m:.4g} ± {sd:.2g} | {alt} |")
     return "\n".join(rows)
 
@@ -146,6 +149,8 @@ def main(argv=None):
     ap.add_argument("--eta-lo", type=float, default=230.0)
     ap.add_argument("--records", type=str, default=None,
                     help="append the records of each run's averaging window here (JSON lines)")
+    ap.add_argument("--autotune-cache", type=str, default=None,
+                    help="file of stored autotuner choices (mts_autotune_cached)")
     ap.add_argument("--summarize", type=str, nargs="+", default=None,
                     help="record files to summarise (no runs)")
     a = ap.parse_args(argv)
@@ -161,7 +166,7 @@ def main(argv=None):
     rec_file = open(a.records, "a") if a.records else None
     for seed in a.seeds:
         eta_lo = a.eta_lo if a.n == 1024 else a.eta_lo * a.n / 1024.0
-        records, asym = run(a.n, a.era, seed, m_damp=a.m_damp, eta_lo=eta_lo)
+        records, asym = run(a.n, a.era, seed, m_damp=a.m_damp, eta_lo=eta_lo, tune_cache=a.autotune_cache)
         if rec_file:
             for r in records:
                 if r["eta"] >= eta_lo:

@@ -58,5 +58,6 @@ def test_summarize_files_recomputes_per_seed_values(tmp_path):
     t = V.table(groups)
     row = next(line for line in t.splitlines() if "| xi_W_dot |" in line)
     assert f"{0.2 * math.sqrt(1.5):.4g}" in row
-    vrow = next(line for line in t.splitlines() if "| v2_lag |" in line)
-    assert vrow.rstrip().endswith("|  |")
+    for key in ("v2_lag", "xi_lag_dot", "f_p"):       # not lengths counted from windings
+        row = next(line for line in t.splitlines() if f"| {key} |" in line)
+        assert row.rstrip().endswith("|  |"), key

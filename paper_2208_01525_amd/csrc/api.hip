@@ -91,6 +91,7 @@ struct mts_ctx {
     int mcur = 0;                // which momentum copy is current: 0 = the state buffer, 1 = mom2
     void *alpha = nullptr;       // arg(phi) per sector: T[2][plane]
     uint8_t *wabs = nullptr;     // packed |W| per sector: [2][plane]
+    uint32_t *fixlist = nullptr; // marked sites of a fused diagnostic step (FP32): FIX_LIST_WORDS words
     uint8_t *cells = nullptr;    // cell values per sector: [2][plane]
     uint64_t *bits = nullptr;    // occupancy words per sector: [2][overlap_words] (nx % 64 == 0)
     double *ring = nullptr;      // [RING_CAP][NSLOT]
@@ -308,7 +309,8 @@ bool diag_writes_alpha(const mts_ctx *c) { return !diag_per_site(c) && c->p.prec
 // residual in the same pass (the post-step kernels then only form the cells
 // and the overlap) unless switched off or no second momentum copy fits.
 bool diag_fused(const mts_ctx *c) {
-    return !diag_per_site(c) && c->p.precision == MTS_FP32 && c->fuse_ty != 0 && !c->fuse_off;
+    return !diag_per_site(c) && c->p.precision == MTS_FP32 && c->fuse_ty != 0 && !c->fuse_off &&
+           c->S < (1ull << 31);   // the fix-up list stores a site in 31 bits
 }
 
 TileShape fused_tile(const mts_ctx *c) { return TileShape{c->fuse_ty, c->tile.tz}; }
@@ -349,7 +351,8 @@ hipError_t enqueue_diag_post(mts_ctx *c, const Book &b, double eta_j, double s, 
             e = launch_wind_gauss<T>(c->g, fields_of<T>(c, c->cur), moms_of<T>(c), alpha, (T)p.dx, (T)(1.0 / p.dx),
                                      gcoef, c->wabs, (uint32_t)c->plane, nullptr, part, st);
     } else {
-        e = launch_wind_fix<T>(c->g, fields_of<T>(c, c->cur), (T)p.dx, c->wabs, (uint32_t)c->plane, part, st);
+        e = launch_wind_fix<T>(c->g, fields_of<T>(c, c->cur), (T)p.dx, c->wabs, (uint32_t)c->plane, part, c->fixlist,
+                               st);
     }
     if (e == hipSuccess) e = launch_cells(c->g, c->wabs, c->cells, c->bits, (uint32_t)c->plane, st);
     if (e == hipSuccess)
@@ -631,6 +634,8 @@ int mts_create(const mts_params *p, void *dev_state, size_t state_bytes, void *s
     if (e == hipSuccess && overlap_uses_bits(c->g))
         e = hipMalloc(&c->bits, sizeof(uint64_t) * 2 * (size_t)overlap_words(c->g));
     if (e == hipSuccess) e = hipMalloc(&c->ring, sizeof(double) * NSLOT * RING_CAP);
+    if (e == hipSuccess && p->precision == MTS_FP32)
+        e = hipMalloc(&c->fixlist, sizeof(uint32_t) * (size_t)FIX_LIST_WORDS);
     if (e == hipSuccess) e = upload_nblk(c);
     if (e != hipSuccess) {
         std::fprintf(stderr, "mts_create: scratch allocation failed: %s\n", hipGetErrorString(e));
@@ -659,6 +664,7 @@ int mts_destroy(mts_ctx *c) {
     (void)hipFree(c->alpha);
     (void)hipFree(c->bits);
     (void)hipFree(c->ring);
+    (void)hipFree(c->fixlist);
     (void)hipFree(c->mom2);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
@@ -1456,6 +1462,7 @@ int batch_upload_boxes(mts_batch *b) {
         q.f[1] = fields_of<T>(c, 1);
         q.part = Partials{c->partials, c->maxblk};
         q.wabs = c->wabs;
+        q.fixlist = c->fixlist;
         q.cells = c->cells;
         q.bits = overlap_uses_bits(c->g) ? c->bits : nullptr;
         q.plane = (uint32_t)c->plane;
@@ -1467,7 +1474,7 @@ int batch_upload_boxes(mts_batch *b) {
         q.blk_fix = bfix;
         q.blk_cells = bcells;
         q.blk_ov = bov;
-        bfix += wind_fix_blocks(c->g);
+        bfix += wind_fix_scan_blocks(c->g);
         bcells += cells_blocks(c->g);
         bov += overlap_blocks(c->g);
     }
@@ -1754,7 +1761,7 @@ int mts_batch_create(const mts_params *boxes, int32_t nbox, void *dev_pool, size
     // FP32 ensembles with diagnostics fuse them when every box has room for a second momentum copy
     if (rc == MTS_OK && b->precision == MTS_FP32 && boxes[0].diag_every > 0) {
         bool room = true;
-        for (mts_ctx *c : b->box) room = room && ensure_mom2_quiet(c) == MTS_OK;
+        for (mts_ctx *c : b->box) room = room && c->S < (1ull << 31) && ensure_mom2_quiet(c) == MTS_OK;
         b->fused = room;
     }
     if (rc == MTS_OK) rc = batch_upload(b);
@@ -1885,6 +1892,8 @@ int mts_batch_set_fused_diagnostics(mts_batch *b, int32_t rows) {
     BHIPCHK(b, hipStreamSynchronize(b->user));
     if (rows) {
         for (size_t k = 0; k < b->box.size(); k++) {
+            if (b->box[k]->S >= (1ull << 31))
+                return bfail(b, MTS_EINVAL, "fused diagnostics: box " + std::to_string(k) + " has 2^31 sites or more");
             const int rc = ensure_mom2(b->box[k], "fused diagnostics");
             if (rc != MTS_OK) return bfail(b, rc, "box " + std::to_string(k) + ": " + b->box[k]->err);
         }

@@ -147,32 +147,42 @@ hipError_t launch_wind_gauss(const Geom &g, Fields<T> f, Moms<T> mom, const T *a
 
 // ---------------------------------------------------------------- fix-up of the fused windings
 
-uint32_t wind_fix_blocks(const Geom &g) { return fix_blocks_of(g.nxy * (uint32_t)g.nz); }
+uint32_t wind_fix_scan_blocks(const Geom &g) { return fix_blocks_of(g.nxy * (uint32_t)g.nz); }
+uint32_t wind_fix_blocks(const Geom &g) { return wind_fix_scan_blocks(g) + FIX_PROC_BLOCKS; }
 
 // The fused diagnostic step marks (WABS_FIX) the sites whose windings used a
 // link the guard sends to FP64; here each marked site's three faces are
 // evaluated as the post-step kernel does, its byte rewritten and its sum |W|
 // added to the SL_FIX_P / SL_FIX_Q partials (the fused kernel counted nothing
-// for it).  A thread scans 16 sites per sector and pass with one 16-byte
-// load (the sector's byte plane is padded to a multiple of 64 sites); at
-// most FIX_MAX_BLOCKS blocks, each looping over its chunks of the box.
+// for it): a scan that lists the marked sites (16 per thread and pass, one
+// 16-byte load per sector; the sector's byte plane is padded to a multiple
+// of 64 sites), then a pass that evaluates the list with every lane busy.
+
 template <typename T>
-__global__ __launch_bounds__(256) void wind_fix_kernel(Geom g, Fields<T> f, T h, uint8_t *wabs, uint32_t plane,
-                                                       Partials part) {
-    fix_block(g, f, h, wabs, plane, part, blockIdx.x, gridDim.x, threadIdx.x);
+__global__ __launch_bounds__(256) void wind_fix_scan_kernel(Geom g, Fields<T> f, T h, uint8_t *wabs, uint32_t plane,
+                                                            Partials part, uint32_t *list) {
+    fix_scan_block(g, f, h, wabs, plane, part, blockIdx.x, gridDim.x, threadIdx.x, list);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void wind_fix_proc_kernel(Geom g, Fields<T> f, T h, uint8_t *wabs, uint32_t plane,
+                                                            Partials part, const uint32_t *list, uint32_t nscan) {
+    fix_proc_block(g, f, h, wabs, plane, part, nscan, nscan, blockIdx.x, gridDim.x, threadIdx.x, list);
 }
 
 template <typename T>
 hipError_t launch_wind_fix(const Geom &g, Fields<T> f, T h, uint8_t *wabs, uint32_t plane, Partials part,
-                           hipStream_t st) {
-    wind_fix_kernel<T><<<wind_fix_blocks(g), 256, 0, st>>>(g, f, h, wabs, plane, part);
+                           uint32_t *list, hipStream_t st) {
+    const uint32_t nscan = wind_fix_scan_blocks(g);
+    wind_fix_scan_kernel<T><<<nscan, 256, 0, st>>>(g, f, h, wabs, plane, part, list);
+    wind_fix_proc_kernel<T><<<FIX_PROC_BLOCKS, 256, 0, st>>>(g, f, h, wabs, plane, part, list, nscan);
     return hipGetLastError();
 }
 
 template hipError_t launch_wind_fix<float>(const Geom &, Fields<float>, float, uint8_t *, uint32_t, Partials,
-                                           hipStream_t);
+                                           uint32_t *, hipStream_t);
 template hipError_t launch_wind_fix<double>(const Geom &, Fields<double>, double, uint8_t *, uint32_t, Partials,
-                                            hipStream_t);
+                                            uint32_t *, hipStream_t);
 
 // ---------------------------------------------------------------- cells
 
@@ -278,11 +288,21 @@ __device__ __forceinline__ Partials part_global(Partials p) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void fix_batch_kernel(const BatchPost<T> *boxes, int nbox, int parity) {
+__global__ __launch_bounds__(256) void fix_scan_batch_kernel(const BatchPost<T> *boxes, int nbox, int parity) {
     const int k = box_of(boxes, nbox, blockIdx.x, &BatchPost<T>::blk_fix);
     const BatchPost<T> &b = boxes[k];
-    fix_block(b.g, fields_global(b.f[parity]), b.h, as_global(b.wabs), b.plane, part_global(b.part),
-              blockIdx.x - b.blk_fix, fix_blocks_of(b.g.nxy * (uint32_t)b.g.nz), threadIdx.x);
+    fix_scan_block(b.g, fields_global(b.f[parity]), b.h, as_global(b.wabs), b.plane, part_global(b.part),
+                   blockIdx.x - b.blk_fix, fix_blocks_of(b.g.nxy * (uint32_t)b.g.nz), threadIdx.x,
+                   as_global(b.fixlist));
+}
+
+// FIX_PROC_BLOCKS blocks per box, box-major
+template <typename T>
+__global__ __launch_bounds__(256) void fix_proc_batch_kernel(const BatchPost<T> *boxes, int parity) {
+    const BatchPost<T> &b = boxes[blockIdx.x / FIX_PROC_BLOCKS];
+    const uint32_t nscan = fix_blocks_of(b.g.nxy * (uint32_t)b.g.nz);
+    fix_proc_block(b.g, fields_global(b.f[parity]), b.h, as_global(b.wabs), b.plane, part_global(b.part), nscan,
+                   nscan, blockIdx.x % FIX_PROC_BLOCKS, FIX_PROC_BLOCKS, threadIdx.x, as_global(b.fixlist));
 }
 
 template <typename T>
@@ -325,7 +345,8 @@ uint32_t cells_blocks(const Geom &g) {
 template <typename T>
 hipError_t launch_post_batch(const BatchPost<T> *boxes_dev, int nbox, uint32_t nfix, uint32_t ncells, uint32_t nov,
                              int parity, uint32_t ring_idx, hipStream_t st) {
-    fix_batch_kernel<T><<<nfix, 256, 0, st>>>(boxes_dev, nbox, parity);
+    fix_scan_batch_kernel<T><<<nfix, 256, 0, st>>>(boxes_dev, nbox, parity);
+    fix_proc_batch_kernel<T><<<(uint32_t)nbox * FIX_PROC_BLOCKS, 256, 0, st>>>(boxes_dev, parity);
     cells_batch_kernel<T><<<ncells, 256, 0, st>>>(boxes_dev, nbox, ncells);
     overlap_batch_kernel<T><<<nov, 256, 0, st>>>(boxes_dev, nbox);
     reduce_batch_kernel<T><<<dim3(NSLOT, (unsigned)nbox, 1), 1024, 0, st>>>(boxes_dev, ring_idx);

@@ -168,6 +168,7 @@ struct BatchPost {
     Fields<T> f[2];       // field copies 0 and 1 (the step's input copy is `parity`)
     Partials part;
     uint8_t *wabs, *cells;
+    uint32_t *fixlist;    // the box's list of marked sites (fix-up)
     uint64_t *bits;       // occupancy words (nx % 64 == 0); null: the byte overlap
     uint32_t plane, nwords;
     int32_t radius;
@@ -234,9 +235,18 @@ uint32_t wind_blocks(const Geom &g);
 // Sites the fused diagnostic step marked WABS_FIX: their windings evaluated
 // with the guarded link phases of the post-step kernel, bytes rewritten,
 // sum |W| into slots SL_FIX_P / SL_FIX_Q (wind_fix_blocks partials).
+// The fix-up of the fused windings: a scan that lists the marked sites,
+// then a pass that evaluates the list (FIX_PROC_BLOCKS blocks per box).
+// list: FIX_LIST_WORDS words per box (a count per scan block, then each
+// block's segment of entries).  wind_fix_blocks: the partials of the SL_FIX
+// slots (scan blocks, then the evaluation blocks); wind_fix_scan_blocks: the
+// scan's.
+constexpr uint32_t FIX_LIST_WORDS = 1024u + 1024u * 1024u;
+constexpr uint32_t FIX_PROC_BLOCKS = 128;
 uint32_t wind_fix_blocks(const Geom &g);
+uint32_t wind_fix_scan_blocks(const Geom &g);
 template <typename T>
-hipError_t launch_wind_fix(const Geom &g, Fields<T> f, T h, uint8_t *wabs, uint32_t plane, Partials part,
+hipError_t launch_wind_fix(const Geom &g, Fields<T> f, T h, uint8_t *wabs, uint32_t plane, Partials part, uint32_t *list,
                            hipStream_t st);
 
 // Cell values from packed |W| (cells[2][plane] bytes) and, when nx is a

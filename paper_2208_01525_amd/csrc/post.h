@@ -91,55 +91,154 @@ constexpr uint32_t FIX_MAX_BLOCKS = 1024;
 
 // Blocks of the fix-up scan of a box of S sites: one pass each up to
 // FIX_MAX_BLOCKS, then several passes per block.  Nearly every byte it reads
-// is unmarked, so the scan is a stream of 16-byte loads; few blocks that
-// loop keep it near the bandwidth of that stream, where one short-lived
-// block per 4096 sites spent most of its time starting and reducing.
+// is unmarked, so the scan is a stream of 16-byte loads.
 __host__ __device__ inline uint32_t fix_blocks_of(uint32_t S) {
     const uint32_t chunks = (S + FIX_CHUNK - 1) / FIX_CHUNK;
     return chunks < FIX_MAX_BLOCKS ? chunks : FIX_MAX_BLOCKS;
 }
 
-// Virtual block lblk of nblk scans the chunks lblk, lblk + nblk, ... of the
-// box; every marked site's three faces are evaluated in FP64 where the guard
-// asks for it (face_windings), its byte rewritten and |W| summed (integers:
-// the partials do not depend on how the chunks are dealt).
+// One marked site of one sector: its three faces evaluated as the post-step
+// kernel does (FP64 from the complex products where the guard asks for it),
+// its byte rewritten; returns |Wx| + |Wy| + |Wz|.
 template <typename T>
-__device__ __forceinline__ void fix_block(const Geom &g, const Fields<T> &f, T h, uint8_t *wabs, uint32_t plane,
-                                          Partials part, uint32_t lblk, uint32_t nblk, uint32_t tid, int group = 0,
-                                          bool valid = true) {
+__device__ __forceinline__ int fix_site(const Geom &g, const Fields<T> &f, T h, uint8_t *wabs, uint32_t plane, int sec,
+                                        uint32_t s) {
+    const cx<T> *P = f.phi[sec];
+    const T *Ax = f.A[sec][0], *Ay = f.A[sec][1], *Az = f.A[sec][2];
+    const int x = s % g.nx, y = (s / g.nx) % g.ny, z = s / g.nxy;
+    const uint32_t nx = g.nx, nxy = g.nxy;
+    const int xp = wrap1(x + 1, g.nx), yp = wrap1(y + 1, g.ny), zp = wrap1(z + 1, g.nz);
+    const uint32_t s_x = xp + nx * y + nxy * z, s_y = x + nx * yp + nxy * z, s_z = x + nx * y + nxy * zp;
+    const uint32_t s_xy = xp + nx * yp + nxy * z, s_xz = xp + nx * y + nxy * zp;
+    const uint32_t s_yz = x + nx * yp + nxy * zp;
+    int Wx, Wy, Wz;
+    face_windings(h, P, phase_of(P[s]), phase_of(P[s_x]), phase_of(P[s_y]), phase_of(P[s_z]), phase_of(P[s_xy]),
+                  phase_of(P[s_xz]), phase_of(P[s_yz]), Ax[s], Ay[s], Az[s], Ay[s_x], Az[s_x], Ax[s_y], Az[s_y],
+                  Ax[s_z], Ay[s_z], s, s_x, s_y, s_z, s_xy, s_xz, s_yz, Wx, Wy, Wz);
+    wabs[(size_t)sec * plane + s] = pack_wabs(Wx, Wy, Wz);
+    return abs(Wx) + abs(Wy) + abs(Wz);
+}
+
+// The fix-up in two passes.  Marked sites are rare per wave but, at early
+// times, not rare per box, and each costs a chain of FP64 work: evaluated by
+// the scanning thread, one lane at a time, they held a wave for the sum of
+// its sites' chains.  So the scan only lists them (entry: sector << 31 |
+// site; the box has fewer than 2^31 sites), and a second pass evaluates the
+// list with every lane busy.  Each scan block owns a segment of FIX_SEG
+// entries and counts into LDS (one global counter for the whole box had
+// serialised its atomics: 0.49 ms at 512^3); it writes its count at the end,
+// so the list needs no clearing.  A block's entries past FIX_SEG are
+// evaluated by the scan itself.  Both passes add integer |W| sums, so the
+// partials do not depend on the order of the list.
+//   list: counts[FIX_MAX_BLOCKS], then entries[FIX_MAX_BLOCKS][FIX_SEG]
+constexpr uint32_t FIX_SEG = 1024;
+static_assert(FIX_LIST_WORDS == FIX_MAX_BLOCKS + FIX_MAX_BLOCKS * FIX_SEG, "list layout");
+
+// Scan: virtual block lblk of nblk walks the chunks lblk, lblk + nblk, ...
+// (partials at lblk; zero unless its segment overflowed).  Every lane of
+// each wave takes part (wave-wide prefix sum and ballot).
+template <typename T>
+__device__ __forceinline__ void fix_scan_block(const Geom &g, const Fields<T> &f, T h, uint8_t *wabs, uint32_t plane,
+                                               Partials part, uint32_t lblk, uint32_t nblk, uint32_t tid,
+                                               uint32_t *list, int group = 0, bool valid = true) {
+    __shared__ uint32_t s_cnt[16];
     const uint32_t S = g.nxy * (uint32_t)g.nz;
+    const int lane = tid & 63;
+    if (tid == 0) s_cnt[group] = 0u;
+    __syncthreads();
+    uint32_t *seg = list + FIX_MAX_BLOCKS + (size_t)lblk * FIX_SEG;
     double acc[2] = {0, 0};
     for (uint32_t c = lblk; valid && c * FIX_CHUNK < S; c += nblk) {
         const uint32_t s0 = c * FIX_CHUNK + tid * FIX_SITES;
-        if (s0 >= S) continue;
+        uint32_t m[2] = {0, 0};   // bit k: site s0 + k is marked
+        if (s0 < S) {
+#pragma unroll
+            for (int sec = 0; sec < 2; sec++) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(wabs + (size_t)sec * plane + s0);
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+#pragma unroll
+                    for (int b = 0; b < 4; b++)
+                        if ((w[q] >> (8 * b)) & WABS_FIX) m[sec] |= 1u << (4 * q + b);
+                if (s0 + FIX_SITES > S) m[sec] &= (1u << (S - s0)) - 1u;   // the plane's padding
+            }
+        }
+        const uint32_t n = (uint32_t)(__popc(m[0]) + __popc(m[1]));
+        if (__ballot(n != 0) == 0) continue;   // the common case: nothing marked in the wave's sites
+        uint32_t incl = n;                     // inclusive prefix sum over the wave
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t t = (uint32_t)__shfl_up((int)incl, d, 64);
+            if (lane >= d) incl += t;
+        }
+        const uint32_t total = (uint32_t)__shfl((int)incl, 63, 64);
+        uint32_t base = 0;
+        if (lane == 63) base = atomicAdd(&s_cnt[group], total);
+        base = (uint32_t)__shfl((int)base, 63, 64);
+        uint32_t idx = base + incl - n;
 #pragma unroll
         for (int sec = 0; sec < 2; sec++) {
-            uint8_t *wb = wabs + (size_t)sec * plane + s0;
-            const uint4 v = *reinterpret_cast<const uint4 *>(wb);
-            constexpr uint32_t M = 0x01010101u * WABS_FIX;
-            if (!((v.x | v.y | v.z | v.w) & M)) continue;
-            const cx<T> *P = f.phi[sec];
-            const T *Ax = f.A[sec][0], *Ay = f.A[sec][1], *Az = f.A[sec][2];
-            for (int k = 0; k < FIX_SITES; k++) {
-                const uint32_t s = s0 + k;
-                if (s >= S || !(wb[k] & WABS_FIX)) continue;
-                const int x = s % g.nx, y = (s / g.nx) % g.ny, z = s / g.nxy;
-                const uint32_t nx = g.nx, nxy = g.nxy;
-                const int xp = wrap1(x + 1, g.nx), yp = wrap1(y + 1, g.ny), zp = wrap1(z + 1, g.nz);
-                const uint32_t s_x = xp + nx * y + nxy * z, s_y = x + nx * yp + nxy * z, s_z = x + nx * y + nxy * zp;
-                const uint32_t s_xy = xp + nx * yp + nxy * z, s_xz = xp + nx * y + nxy * zp;
-                const uint32_t s_yz = x + nx * yp + nxy * zp;
-                int Wx, Wy, Wz;
-                face_windings(h, P, phase_of(P[s]), phase_of(P[s_x]), phase_of(P[s_y]), phase_of(P[s_z]),
-                              phase_of(P[s_xy]), phase_of(P[s_xz]), phase_of(P[s_yz]), Ax[s], Ay[s], Az[s], Ay[s_x],
-                              Az[s_x], Ax[s_y], Az[s_y], Ax[s_z], Ay[s_z], s, s_x, s_y, s_z, s_xy, s_xz, s_yz, Wx,
-                              Wy, Wz);
-                wb[k] = pack_wabs(Wx, Wy, Wz);
-                acc[sec] += (double)(abs(Wx) + abs(Wy) + abs(Wz));
+            uint32_t mm = m[sec];
+            while (mm) {
+                const int k = __ffs(mm) - 1;
+                mm &= mm - 1;
+                const uint32_t s = s0 + (uint32_t)k;
+                if (idx < FIX_SEG) seg[idx] = ((uint32_t)sec << 31) | s;
+                else acc[sec] += (double)fix_site(g, f, h, wabs, plane, sec, s);
+                idx++;
             }
         }
     }
+    __syncthreads();
+    if (tid == 0 && valid) list[lblk] = s_cnt[group];
     group_sum_store<2>(acc, part, SL_FIX_P, lblk, group, valid);
+}
+
+// Evaluation of the listed sites of a box whose scan had nscan blocks: block
+// pblk of nproc (256 threads) deals the entries of all segments out evenly,
+// by a prefix sum of the segment counts in LDS, so every lane holds an entry
+// while entries remain (partials at pblk0 + pblk).
+template <typename T>
+__device__ __forceinline__ void fix_proc_block(const Geom &g, const Fields<T> &f, T h, uint8_t *wabs, uint32_t plane,
+                                               Partials part, uint32_t nscan, uint32_t pblk0, uint32_t pblk,
+                                               uint32_t nproc, uint32_t tid, const uint32_t *list) {
+    __shared__ uint32_t s_pre[FIX_MAX_BLOCKS + 1];   // segment counts, then their exclusive prefix sums
+    __shared__ uint32_t s_part[256];
+    for (uint32_t i = tid; i < FIX_MAX_BLOCKS; i += 256) s_pre[i] = i < nscan ? min(list[i], FIX_SEG) : 0u;
+    __syncthreads();
+    uint32_t loc[4], sum = 0;   // thread tid holds segments 4 tid .. 4 tid + 3
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        loc[k] = sum;
+        sum += s_pre[4 * tid + k];
+    }
+    s_part[tid] = sum;
+    __syncthreads();
+    for (uint32_t d = 1; d < 256; d <<= 1) {   // inclusive scan of the 256 sums
+        const uint32_t v = tid >= d ? s_part[tid - d] : 0u;
+        __syncthreads();
+        s_part[tid] += v;
+        __syncthreads();
+    }
+    const uint32_t base = s_part[tid] - sum, total = s_part[255];
+#pragma unroll
+    for (int k = 0; k < 4; k++) s_pre[4 * tid + k] = base + loc[k];
+    if (tid == 0) s_pre[FIX_MAX_BLOCKS] = total;
+    __syncthreads();
+    double acc[2] = {0, 0};
+    for (uint32_t e = pblk * 256 + tid; e < total; e += nproc * 256) {
+        uint32_t lo = 0, hi = nscan - 1;   // last segment with s_pre[lo] <= e
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if (s_pre[mid] <= e) lo = mid;
+            else hi = mid - 1;
+        }
+        const uint32_t entry = list[FIX_MAX_BLOCKS + (size_t)lo * FIX_SEG + (e - s_pre[lo])];
+        const int sec = (int)(entry >> 31);
+        acc[sec] += (double)fix_site(g, f, h, wabs, plane, sec, entry & 0x7FFFFFFFu);
+    }
+    group_sum_store<2>(acc, part, SL_FIX_P, pblk0 + pblk, 0, true);
 }
 
 

@@ -233,7 +233,8 @@ int mts_segments(mts_ctx *ctx, double min_length, mts_segments_t *out, int64_t *
  * not spill registers); every tile shape gives bitwise identical fields, and
  * records that agree to the rounding of their block sums.  ty = 0 selects the one-thread-per-site kernel, which computes
  * the plaquette sines directly and agrees with the tiled kernel to
- * rounding.  Synchronises the stream.  EINVAL for other shapes. */
+ * rounding (tz >= 1 is still required, and kept for the tiled kernels of
+ * the diagnostic steps).  Synchronises the stream.  EINVAL for other shapes. */
 int mts_set_tile(mts_ctx *ctx, int32_t ty, int32_t tz);
 int mts_get_tile(const mts_ctx *ctx, int32_t *ty, int32_t *tz);
 

@@ -91,7 +91,7 @@ struct mts_ctx {
     int mcur = 0;                // which momentum copy is current: 0 = the state buffer, 1 = mom2
     void *alpha = nullptr;       // arg(phi) per sector: T[2][plane]
     uint8_t *wabs = nullptr;     // packed |W| per sector: [2][plane]
-    uint32_t *fixlist = nullptr; // marked sites of a fused diagnostic step (FP32): FIX_LIST_WORDS words
+    uint32_t *fixlist = nullptr; // marked sites of a diagnostic step's windings (fix-up): FIX_LIST_WORDS words
     uint8_t *cells = nullptr;    // cell values per sector: [2][plane]
     uint64_t *bits = nullptr;    // occupancy words per sector: [2][overlap_words] (nx % 64 == 0)
     double *ring = nullptr;      // [RING_CAP][NSLOT]
@@ -323,8 +323,13 @@ hipError_t upload_nblk(mts_ctx *c) {
     uint32_t nb[2 * NSLOT];
     const uint32_t step_blocks = diag_per_site(c) ? site_blocks(c->g) : tile_blocks(c->g, diag_tile(c));
     const uint32_t fused_blocks = c->fuse_ty ? tile_blocks(c->g, fused_tile(c)) : 0;
+    // FP64: the tiled winding/Gauss kernel and the fix-up passes; FP32
+    // without fusion: the per-column winding/Gauss kernel
+    const bool fp64 = c->p.precision == MTS_FP64;
+    const uint32_t wblk = fp64 ? wind_tile_blocks(c->g) : wind_blocks(c->g);
+    const uint32_t fixblk = fp64 ? wind_fix_blocks(c->g) : 0;
     for (int q = 0; q < NSLOT; q++) {
-        nb[q] = q <= SL_GV ? step_blocks : (q <= SL_WIND_Q ? wind_blocks(c->g) : (q <= SL_OV_Q ? overlap_blocks(c->g) : 0));
+        nb[q] = q <= SL_GV ? step_blocks : (q <= SL_WIND_Q ? wblk : (q <= SL_OV_Q ? overlap_blocks(c->g) : fixblk));
         nb[NSLOT + q] = q <= SL_WIND_Q ? fused_blocks : (q <= SL_OV_Q ? overlap_blocks(c->g) : wind_fix_blocks(c->g));
     }
     return hipMemcpy(c->nblk_dev, nb, sizeof(nb), hipMemcpyHostToDevice);
@@ -345,7 +350,18 @@ hipError_t enqueue_diag_post(mts_ctx *c, const Book &b, double eta_j, double s, 
     for (int q = 0; q < 2; q++) gcoef[q] = 2.0 * e2[q] * b.An * (1.0 + b.delta) / (1.0 + b.omega);
     T *alpha = static_cast<T *>(c->alpha);
     hipError_t e = hipSuccess;
-    if (!fused) {
+    if (!fused && sizeof(T) == 8) {
+        // FP64: windings (wrap counts) and the Gauss residual in one tiled
+        // pass, then the fix-up of the flagged sites
+        if constexpr (sizeof(T) == 8) {
+            e = launch_wind_gauss_tile<T>(c->g, fields_of<T>(c, c->cur), moms_of<T>(c), (T)p.dx, (T)(1.0 / p.dx),
+                                          gcoef, c->wabs, (uint32_t)c->plane, part, st);
+            if (e == hipSuccess)
+                e = launch_wind_fix<T>(c->g, fields_of<T>(c, c->cur), (T)p.dx, c->wabs, (uint32_t)c->plane, part,
+                                       c->fixlist, st);
+        }
+        (void)alpha;
+    } else if (!fused) {
         if (!alpha_ready) e = launch_phase<T>(c->g, fields_of<T>(c, c->cur), alpha, (uint32_t)c->plane, st);
         if (e == hipSuccess)
             e = launch_wind_gauss<T>(c->g, fields_of<T>(c, c->cur), moms_of<T>(c), alpha, (T)p.dx, (T)(1.0 / p.dx),
@@ -625,7 +641,7 @@ int mts_create(const mts_params *p, void *dev_state, size_t state_bytes, void *s
     c->maxblk = site_blocks(c->g);
     for (int ty : {4, 5, 8, 12, 13}) c->maxblk = std::max(c->maxblk, tile_blocks(c->g, TileShape{ty, 1}));
     c->maxblk = std::max(c->maxblk, std::max(wind_blocks(c->g), overlap_blocks(c->g)));
-    c->maxblk = std::max(c->maxblk, wind_fix_blocks(c->g));
+    c->maxblk = std::max(c->maxblk, std::max(wind_fix_blocks(c->g), wind_tile_blocks(c->g)));
     hipError_t e = hipMalloc(&c->partials, sizeof(double) * NSLOT * (size_t)c->maxblk);
     if (e == hipSuccess) e = hipMalloc(&c->nblk_dev, sizeof(uint32_t) * 2 * NSLOT);
     if (e == hipSuccess) e = hipMalloc(&c->wabs, 2 * c->plane);
@@ -634,8 +650,7 @@ int mts_create(const mts_params *p, void *dev_state, size_t state_bytes, void *s
     if (e == hipSuccess && overlap_uses_bits(c->g))
         e = hipMalloc(&c->bits, sizeof(uint64_t) * 2 * (size_t)overlap_words(c->g));
     if (e == hipSuccess) e = hipMalloc(&c->ring, sizeof(double) * NSLOT * RING_CAP);
-    if (e == hipSuccess && p->precision == MTS_FP32)
-        e = hipMalloc(&c->fixlist, sizeof(uint32_t) * (size_t)FIX_LIST_WORDS);
+    if (e == hipSuccess) e = hipMalloc(&c->fixlist, sizeof(uint32_t) * (size_t)FIX_LIST_WORDS);
     if (e == hipSuccess) e = upload_nblk(c);
     if (e != hipSuccess) {
         std::fprintf(stderr, "mts_create: scratch allocation failed: %s\n", hipGetErrorString(e));
@@ -903,7 +918,9 @@ int mts_segments(mts_ctx *c, double min_length, mts_segments_t *out, int64_t *si
 int mts_set_tile(mts_ctx *c, int32_t ty, int32_t tz) {
     if (!c) return MTS_EINVAL;
     const TileShape ts{ty, tz};
-    if (ty != 0 && !tile_supported(ts, c->p.precision == MTS_FP64))
+    // tz >= 1 also with ty = 0: the diagnostic paths size their tiled grids
+    // from the stored tz
+    if (tz < 1 || (ty != 0 && !tile_supported(ts, c->p.precision == MTS_FP64)))
         return fail(c, MTS_EINVAL, "tile: ty must be 0, 4, 5, 8, 12 or (FP32) 13 and tz >= 1");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->tile = ts;

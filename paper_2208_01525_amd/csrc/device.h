@@ -258,6 +258,28 @@ __device__ __forceinline__ int link_wrap(T aa, T ab, T hA, bool &flag) {
     return flag ? 0 : (int)n;
 }
 
+// h A of a link, rounded on its own (the same value wherever it is formed)
+template <typename T>
+__device__ __forceinline__ T link_angle(T h, T A) {
+#pragma clang fp contract(off)
+    return h * A;
+}
+
+// Packed wrap counts of a site's three links (x, y, z: 9-bit fields, two's
+// complement) and their guard flags (bits 27, 28, 29).
+__device__ __forceinline__ int wrap_word(int nx, int ny, int nz, bool fx, bool fy, bool fz) {
+    return (nx & 0x1FF) | ((ny & 0x1FF) << 9) | ((nz & 0x1FF) << 18) | ((int)fx << 27) | ((int)fy << 28) |
+           ((int)fz << 29);
+}
+template <int K>
+__device__ __forceinline__ int wrap_n(int w) {
+    return (int)((uint32_t)w << (23 - 9 * K)) >> 23;
+}
+template <int K>
+__device__ __forceinline__ int wrap_f(int w) {
+    return (w >> (27 + K)) & 1;
+}
+
 // chi + h A of a link for the fused diagnostics, or NaN where the guard asks
 // for the FP64 product (near the branch cut or |h A| above Guard::big; a NaN
 // phase, phi = 0 at an end, gives NaN by itself).

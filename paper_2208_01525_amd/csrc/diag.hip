@@ -145,6 +145,250 @@ hipError_t launch_wind_gauss(const Geom &g, Fields<T> f, Moms<T> mom, const T *a
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- windings and Gauss, tiled (FP64)
+//
+// The FP64 diagnostic step's windings and Gauss residual in one z-marching
+// pass over 64 x WG_TY tiles with a one-site halo, as the fused FP32
+// diagnostic tile forms them (the FP64 update tile has no registers left to
+// do it in place): each site's phase alpha of plane z+1 and the new E_x, E_y
+// of plane z go through LDS; each link's wrap count is formed once and
+// packed with its site's others; the winding through a face is minus the
+// oriented sum of its four links' counts; a flagged link (guard, or a count
+// beyond the packed field) marks the site WABS_FIX for the FP64 fix-up
+// passes.  It reads phi, A, E and Pi once per site (the halo rows from L2),
+// each plane's loads issued one plane ahead so that they are in flight
+// across the previous plane's barriers.
+//
+// The phases are FP32 (atan2_fast of the FP64 phi, both components first
+// scaled by one power of two, which is exact), the wrap decision FP64:
+// v = (alpha_b - alpha_a) - h A in double from the widened phases.  Each
+// phase is within 5e-7 rad of the FP64 one (4e-7 from atan2_fast, 6e-8
+// from rounding the scaled components), so v is within about 1e-6 of its
+// FP64 value, and a link with |chi| <= pi - MIXED_CUT has the same count as
+// in FP64; every other link, and every link with a zero, NaN or infinite
+// phi at an end, is flagged and its faces evaluated in FP64 by the fix-up.
+// The windings are therefore those of the FP64 evaluation bit for bit; the
+// Gauss residual is FP64 throughout.
+
+namespace {
+
+constexpr int WG_TY = 8;    // interior rows of a tile (WG_TY + 3 waves: rows, two halo rows, halo columns)
+constexpr int WG_TZ = 32;   // planes per tile
+constexpr int WG_LW = 66;   // LDS row width: 64 + the -x and +x halo columns
+constexpr double MIXED_CUT = 1e-4;   // rad kept from the branch cut by FP32 phases
+
+__device__ __forceinline__ int wrapn(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// FP32 phase of an FP64 phi; NaN for phi = 0 or a non-finite component.
+__device__ __forceinline__ float phase_f32(cx<double> p) {
+    const double mx = fmax(fabs(p.re), fabs(p.im));
+    if (!(mx > 0.0 && mx <= 1.7976931348623157e308)) return __builtin_nanf("");
+    int e;
+    (void)frexp(mx, &e);
+    return atan2_fast((float)ldexp(p.im, -e), (float)ldexp(p.re, -e));
+}
+
+// Wrap count of a link from FP32 phases and the FP64 h A (see above); a
+// count beyond the 9-bit field is left to the fix-up as well.
+__device__ __forceinline__ int link_wrap_mixed(float aa, float ab, double hA, bool &flag) {
+#pragma clang fp contract(off)
+    const double v = ((double)ab - (double)aa) - hA;
+    const double n = rint(v * (0.5 / Pi<double>::v));
+    const double chi = v - (2.0 * Pi<double>::v) * n;
+    flag = !(fabs(chi) <= Pi<double>::v - MIXED_CUT && fabs(hA) <= Guard<double>::big && fabs(n) <= 255.0);
+    return flag ? 0 : (int)n;
+}
+
+}  // namespace
+
+uint32_t wind_tile_blocks(const Geom &g) {
+    return (uint32_t)((g.nx + 63) / 64) * (uint32_t)((g.ny + WG_TY - 1) / WG_TY) *
+           (uint32_t)((g.nz + WG_TZ - 1) / WG_TZ);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64 * (WG_TY + 3)) void wind_gauss_tile_kernel(Geom g, Fields<T> f, Moms<T> mom, T h,
+                                                                            T inv_h, double g_p, double g_q,
+                                                                            uint8_t *wabs, uint32_t plane,
+                                                                            Partials part) {
+    static_assert(sizeof(T) == 8, "FP64 fields");
+    constexpr int TY = WG_TY, R = TY + 2, LW = WG_LW;
+    __shared__ float s_al[2][R * LW];              // alpha of plane z+1
+    __shared__ T s_ex[2][R * LW], s_ey[2][R * LW]; // E_x, E_y (n + 1/2) of plane z
+    __shared__ int s_w[2][R * LW];                 // packed wrap counts of plane z
+    const int ntx = (g.nx + 63) / 64, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + WG_TZ - 1) / WG_TZ;
+    const uint32_t t = xcd_order(blockIdx.x, (uint32_t)(ntx * nty * ntz));
+    const int X0 = (int)(t % ntx) * 64, Y0 = (int)((t / ntx) % nty) * TY, Z0 = (int)(t / (ntx * nty)) * WG_TZ;
+
+    // which site of the tile this thread holds (as the update tile does)
+    const int lx = threadIdx.x, w = threadIdx.y;
+    int row, col;
+    bool owner = true;
+    if (w < TY) {
+        row = w + 1;
+        col = lx + 1;
+    } else if (w == TY) {
+        row = 0;
+        col = lx + 1;
+    } else if (w == TY + 1) {
+        row = R - 1;
+        col = lx + 1;
+    } else if (lx < R) {
+        row = lx;
+        col = 0;
+    } else if (lx < 2 * R) {
+        row = lx - R;
+        col = LW - 1;
+    } else {
+        row = 0;
+        col = 0;
+        owner = false;
+    }
+    const int gx = X0 - 1 + col, gy = Y0 - 1 + row;
+    const int x = wrapn(gx, g.nx), y = wrapn(gy, g.ny);
+    const bool interior = w < TY && gx < g.nx && gy < g.ny;
+    const bool need_ex = owner && (interior || (col == 0 && row >= 1 && row <= TY));   // E_x at x - 1
+    const bool need_ey = owner && (interior || (row == 0 && col >= 1 && col <= LW - 2)); // E_y at y - 1
+    const uint32_t colidx = (uint32_t)x + (uint32_t)g.nx * (uint32_t)y;
+    const int li = row * LW + col;
+    const int lxp = row * LW + min(col + 1, LW - 1), lyp = min(row + 1, R - 1) * LW + col;
+    const int lxm = row * LW + max(col - 1, 0), lym = max(row - 1, 0) * LW + col;
+    const int zbeg = Z0, zend = min(Z0 + WG_TZ, g.nz);
+    const T gs[2] = {(T)g_p, (T)g_q};
+
+    cx<T> cf[2];    // phi of plane z
+    float alc[2];   // its phases
+    T caz[2], ezp[2] = {T(0), T(0)};
+    int wxy[2] = {0, 0};
+    // loaded one plane ahead: phi and A of plane z+1, E and Pi of plane z
+    cx<T> pf[2], ppi[2];
+    T pax[2], pay[2], paz[2], pex[2], pey[2], pez[2];
+    {
+        const uint32_t s = colidx + g.nxy * (uint32_t)wrapn(zbeg - 1, g.nz);
+        const uint32_t sn = colidx + g.nxy * (uint32_t)zbeg;
+#pragma unroll
+        for (int sec = 0; sec < 2; sec++) {
+            cf[sec] = f.phi[sec][s];
+            alc[sec] = phase_f32(cf[sec]);
+            caz[sec] = f.A[sec][2][s];
+            if (interior) ezp[sec] = mom.E[sec][2][s];
+            pf[sec] = f.phi[sec][sn];
+            pax[sec] = f.A[sec][0][sn];
+            pay[sec] = f.A[sec][1][sn];
+            paz[sec] = f.A[sec][2][sn];
+            pex[sec] = pey[sec] = pez[sec] = T(0);
+            ppi[sec] = cx<T>{T(0), T(0)};
+        }
+    }
+    double acc[6] = {0, 0, 0, 0, 0, 0};   // gauss |C| p, q; scale p, q; wind p, q
+    for (int z = zbeg - 1; z < zend; z++) {
+        const bool upd = interior && z >= zbeg;
+        const uint32_t s = colidx + g.nxy * (uint32_t)wrapn(z, g.nz);
+        cx<T> nf[2], pic[2];
+        T nax[2], nay[2], naz[2], exc[2], eyc[2], ezc[2];
+#pragma unroll
+        for (int sec = 0; sec < 2; sec++) {
+            nf[sec] = pf[sec];
+            nax[sec] = pax[sec];
+            nay[sec] = pay[sec];
+            naz[sec] = paz[sec];
+            exc[sec] = pex[sec];
+            eyc[sec] = pey[sec];
+            ezc[sec] = pez[sec];
+            pic[sec] = ppi[sec];
+        }
+        if (z + 1 < zend) {   // the next plane's loads (z+1 < nz; z+2 wraps at the box's end)
+            const uint32_t s1 = colidx + g.nxy * (uint32_t)(z + 1);
+            const uint32_t s2 = colidx + g.nxy * (uint32_t)wrapn(z + 2, g.nz);
+#pragma unroll
+            for (int sec = 0; sec < 2; sec++) {
+                pf[sec] = f.phi[sec][s2];
+                pax[sec] = f.A[sec][0][s2];
+                pay[sec] = f.A[sec][1][s2];
+                paz[sec] = f.A[sec][2][s2];
+                if (need_ex) pex[sec] = mom.E[sec][0][s1];
+                if (need_ey) pey[sec] = mom.E[sec][1][s1];
+                if (interior) {
+                    pez[sec] = mom.E[sec][2][s1];
+                    ppi[sec] = mom.pi[sec][s1];
+                }
+            }
+        }
+        float aln[2];
+#pragma unroll
+        for (int sec = 0; sec < 2; sec++) {
+            aln[sec] = phase_f32(nf[sec]);
+            if (owner) s_al[sec][li] = aln[sec];
+            if (z >= zbeg) {
+                if (need_ex) s_ex[sec][li] = exc[sec];
+                if (need_ey) s_ey[sec][li] = eyc[sec];
+            }
+        }
+        __syncthreads();
+        // wrap counts of the x and y links of plane z+1 and of the z link of
+        // plane z (garbage where the neighbour lies outside the tile: no face
+        // reads those); the word of plane z staged
+        int wnext[2], wown[2];
+#pragma unroll
+        for (int sec = 0; sec < 2; sec++) {
+            bool fx, fy, fz;
+            const int nx_ = link_wrap_mixed(aln[sec], s_al[sec][lxp], link_angle(h, nax[sec]), fx);
+            const int ny_ = link_wrap_mixed(aln[sec], s_al[sec][lyp], link_angle(h, nay[sec]), fy);
+            const int nz_ = link_wrap_mixed(alc[sec], aln[sec], link_angle(h, caz[sec]), fz);
+            wnext[sec] = wrap_word(nx_, ny_, 0, fx, fy, false);
+            wown[sec] = wxy[sec] | wrap_word(0, 0, nz_, false, false, fz);
+            if (owner) s_w[sec][li] = wown[sec];
+        }
+        __syncthreads();
+        if (upd) {
+#pragma unroll
+            for (int sec = 0; sec < 2; sec++) {
+                // windings through the three faces at the site (lower corner x)
+                const int o = wown[sec], xp = s_w[sec][lxp], yp = s_w[sec][lyp], zp = wnext[sec];
+                const int Wz = -(((wrap_n<0>(o) + wrap_n<1>(xp)) - wrap_n<0>(yp)) - wrap_n<1>(o));
+                const int Wx = -(((wrap_n<1>(o) + wrap_n<2>(yp)) - wrap_n<1>(zp)) - wrap_n<2>(o));
+                const int Wy = -(((wrap_n<2>(o) + wrap_n<0>(zp)) - wrap_n<2>(xp)) - wrap_n<0>(o));
+                const int flagged = (wrap_f<0>(o) | wrap_f<1>(o) | wrap_f<2>(o)) | wrap_f<1>(xp) | wrap_f<2>(xp) |
+                                    wrap_f<0>(yp) | wrap_f<2>(yp) | wrap_f<0>(zp) | wrap_f<1>(zp);
+                uint8_t byte = WABS_FIX;
+                if (!flagged) {
+                    byte = pack_wabs(Wx, Wy, Wz);
+                    acc[4 + sec] += (double)(abs(Wx) + abs(Wy) + abs(Wz));
+                }
+                wabs[(size_t)sec * plane + s] = byte;
+                // Gauss residual at n + 1/2: div E^{n+1/2} - g Im[conj(phi^n) Pi^{n+1/2}]
+                const T div = gauss_div(s_ex[sec][li], s_ex[sec][lxm], s_ey[sec][li], s_ey[sec][lym], ezc[sec],
+                                        ezp[sec], inv_h);
+                gauss_accumulate(div, gauss_charge(gs[sec], cf[sec], pic[sec]), acc[sec], acc[2 + sec]);
+                ezp[sec] = ezc[sec];
+            }
+        }
+        __syncthreads();   // LDS of plane z is reused by plane z+1
+#pragma unroll
+        for (int sec = 0; sec < 2; sec++) {
+            cf[sec] = nf[sec];
+            alc[sec] = aln[sec];
+            caz[sec] = naz[sec];
+            wxy[sec] = wnext[sec];
+        }
+    }
+    block_sum_store<6, TY + 3>(acc, part, SL_GAUSS_ABS_P, blockIdx.x);
+}
+
+template <typename T>
+hipError_t launch_wind_gauss_tile(const Geom &g, Fields<T> f, Moms<T> mom, T h, T inv_h, const double gcoef[2],
+                                  uint8_t *wabs, uint32_t plane, Partials part, hipStream_t st) {
+    wind_gauss_tile_kernel<T><<<wind_tile_blocks(g), dim3(64, WG_TY + 3, 1), 0, st>>>(
+        g, f, mom, h, inv_h, gcoef[0], gcoef[1], wabs, plane, part);
+    return hipGetLastError();
+}
+
+template hipError_t launch_wind_gauss_tile<double>(const Geom &, Fields<double>, Moms<double>, double, double,
+                                                   const double[2], uint8_t *, uint32_t, Partials, hipStream_t);
+
 // ---------------------------------------------------------------- fix-up of the fused windings
 
 uint32_t wind_fix_scan_blocks(const Geom &g) { return fix_blocks_of(g.nxy * (uint32_t)g.nz); }

@@ -245,6 +245,14 @@ constexpr uint32_t FIX_LIST_WORDS = 1024u + 1024u * 1024u;
 constexpr uint32_t FIX_PROC_BLOCKS = 128;
 uint32_t wind_fix_blocks(const Geom &g);
 uint32_t wind_fix_scan_blocks(const Geom &g);
+
+// FP64 diagnostic steps: windings (wrap counts, flagged sites marked for the
+// fix-up) and the Gauss residual in one z-marching pass of 64 x 8 tiles;
+// partials SL_GAUSS_ABS_P .. SL_WIND_Q per block (wind_tile_blocks).
+uint32_t wind_tile_blocks(const Geom &g);
+template <typename T>
+hipError_t launch_wind_gauss_tile(const Geom &g, Fields<T> f, Moms<T> mom, T h, T inv_h, const double gcoef[2],
+                                  uint8_t *wabs, uint32_t plane, Partials part, hipStream_t st);
 template <typename T>
 hipError_t launch_wind_fix(const Geom &g, Fields<T> f, T h, uint8_t *wabs, uint32_t plane, Partials part, uint32_t *list,
                            hipStream_t st);

@@ -64,20 +64,6 @@ struct FusedLds {
     int nw[2][(TY + 2) * LW]; // the plane's packed link wrap counts, every site of the tile
 };
 
-// Packed wrap counts of a site's three links (x, y, z: 9-bit fields, two's
-// complement) and their guard flags (bits 27, 28, 29).
-__device__ __forceinline__ int wrap_word(int nx, int ny, int nz, bool fx, bool fy, bool fz) {
-    return (nx & 0x1FF) | ((ny & 0x1FF) << 9) | ((nz & 0x1FF) << 18) | ((int)fx << 27) | ((int)fy << 28) |
-           ((int)fz << 29);
-}
-template <int K>
-__device__ __forceinline__ int wrap_n(int w) {
-    return (int)((uint32_t)w << (23 - 9 * K)) >> 23;
-}
-template <int K>
-__device__ __forceinline__ int wrap_f(int w) {
-    return (w >> (27 + K)) & 1;
-}
 template <typename T, int TY>
 struct NoFusedLds {};
 
@@ -86,11 +72,6 @@ template <typename T>
 __device__ __forceinline__ T link_value(T chi, T hA) {
 #pragma clang fp contract(off)
     return chi + hA;
-}
-template <typename T>
-__device__ __forceinline__ T link_angle(T h, T A) {
-#pragma clang fp contract(off)
-    return h * A;
 }
 
 }  // namespace

@@ -104,10 +104,10 @@ def test_fused_checkpoint_resume_and_switching():
     b.close()
 
 
-def _planted(nx, ny, nz, seed):
+def _planted(nx, ny, nz, seed, f32=True, offsets=(-3e-5, 3e-5, 1e-6)):
     """Random fields with the cases the winding guard sends to FP64 planted: zeros of
-    phi, link angles above 1e3, and links whose phase lies within 3e-5 of the branch cut
-    on either side (values rounded to float32 as the lattice holds them)."""
+    phi, link angles above 1e3, and links whose phase lies at the given offsets from the
+    branch cut (values rounded to float32 as the lattice holds them, unless f32 is off)."""
     rng = np.random.default_rng(seed)
     st = I.random_full(nx, ny, nz, seed, link=0.8, mom=0.5)
     S = nx * ny * nz
@@ -123,9 +123,9 @@ def _planted(nx, ny, nz, seed):
             i = int(rng.integers(3))
             t = (x + (i == 0)) % nx + nx * ((y + (i == 1)) % ny) + nx * ny * ((z + (i == 2)) % nz)
             phase = lambda k: np.arctan2(flat[c + 1, k], flat[c, k])
-            target = np.pi - rng.choice([-3e-5, 3e-5, 1e-6])
+            target = np.pi - rng.choice(offsets)
             flat[a0 + i, s] = (phase(t) - phase(s) - target) / h
-    return I.to_f32_values(st)
+    return I.to_f32_values(st) if f32 else st
 
 
 @pytest.mark.parametrize("rows", [5, 8])
@@ -150,6 +150,34 @@ def test_fused_guard_cases_match_oracle(rows):
         assert rec["wind_abs"] == (int(np.abs(W[:3]).sum()), int(np.abs(W[3:]).sum()))
         assert np.array_equal(lat.get_cells().astype(np.int32), ref_cells)
         lat.close()
+
+
+@pytest.mark.parametrize("tile", [None, 0])
+def test_fp64_guard_cases_match_oracle(tile):
+    """FP64 diagnostic steps form wrap counts from FP32 phases of the FP64 fields and
+    flag every link within 1e-4 rad of the branch cut: links planted just inside that
+    margin (3e-5, 1e-6, 1e-12 from the cut) go to the FP64 fix-up, links just outside it
+    (2e-4) keep the fast count; both equal the oracle's windings exactly, with zeros of
+    phi and link angles above 1e3, on the tiled and on the per-site diagnostic update."""
+    nx, ny, nz = 72, 18, 11
+    st = _planted(nx, ny, nz, 37, f32=False, offsets=(-3e-5, 3e-5, 1e-6, 1e-12, -2e-4, 2e-4))
+    m = O.model(nx, ny, nz, eta_ref=9.0, kappa=0.9)
+    W = O.windings(m, st)
+    assert np.abs(W).max() > 3
+    lat = P.Lattice(P.make_params(nx, ny, nz, precision="fp64", eta_ref=9.0, diag_every=1, kappa=0.9),
+                    device="cuda:0")
+    if tile is not None:
+        with pytest.raises(P.MtsError):       # tz >= 1 also for the per-site kernel
+            lat.set_tile(tile, 0)
+        lat.set_tile(tile, 32)
+    lat.set_fields(st)
+    lat.step(1, 3.0, 0.5, 1.0)
+    rec = lat.diagnostics()[0]
+    got = lat.get_cells().astype(np.int32)
+    lat.close()
+    assert rec["wind_abs"] == (int(np.abs(W[:3]).sum()), int(np.abs(W[3:]).sum()))
+    assert np.array_equal(got, O.cells(m, np.clip(W, -3, 3)))
+    assert rec["pq_count2"] == sum(O.overlap(m, O.cells(m, W)))
 
 
 def test_batch_fused_matches_box_by_box():

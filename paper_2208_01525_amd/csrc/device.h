@@ -275,10 +275,9 @@ template <int K>
 __device__ __forceinline__ int wrap_n(int w) {
     return (int)((uint32_t)w << (23 - 9 * K)) >> 23;
 }
-template <int K>
-__device__ __forceinline__ int wrap_f(int w) {
-    return (w >> (27 + K)) & 1;
-}
+// the flag bits a face reads from the words of its corner sites: all three
+// at the site, y and z at +x, x and z at +y, x and y at +z
+constexpr int WRAP_F_XYZ = 7 << 27, WRAP_F_YZ = 6 << 27, WRAP_F_XZ = 5 << 27, WRAP_F_XY = 3 << 27;
 
 // chi + h A of a link for the fused diagnostics, or NaN where the guard asks
 // for the FP64 product (near the branch cut or |h A| above Guard::big; a NaN

@@ -252,6 +252,9 @@ __global__ __launch_bounds__(64 * (WG_TY + 3)) void wind_gauss_tile_kernel(Geom 
     const bool interior = w < TY && gx < g.nx && gy < g.ny;
     const bool need_ex = owner && (interior || (col == 0 && row >= 1 && row <= TY));   // E_x at x - 1
     const bool need_ey = owner && (interior || (row == 0 && col >= 1 && col <= LW - 2)); // E_y at y - 1
+    // the faces read phases and wrap counts at the site and at +x and +y
+    // only: the row y0 - 1 and the column x0 - 1 form neither
+    const bool wraps = owner && row > 0 && col > 0;
     const uint32_t colidx = (uint32_t)x + (uint32_t)g.nx * (uint32_t)y;
     const int li = row * LW + col;
     const int lxp = row * LW + min(col + 1, LW - 1), lyp = min(row + 1, R - 1) * LW + col;
@@ -317,11 +320,13 @@ __global__ __launch_bounds__(64 * (WG_TY + 3)) void wind_gauss_tile_kernel(Geom 
                 }
             }
         }
-        float aln[2];
+        float aln[2] = {0.f, 0.f};
 #pragma unroll
         for (int sec = 0; sec < 2; sec++) {
-            aln[sec] = phase_f32(nf[sec]);
-            if (owner) s_al[sec][li] = aln[sec];
+            if (wraps) {
+                aln[sec] = phase_f32(nf[sec]);
+                s_al[sec][li] = aln[sec];
+            }
             if (z >= zbeg) {
                 if (need_ex) s_ex[sec][li] = exc[sec];
                 if (need_ey) s_ey[sec][li] = eyc[sec];
@@ -331,16 +336,18 @@ __global__ __launch_bounds__(64 * (WG_TY + 3)) void wind_gauss_tile_kernel(Geom 
         // wrap counts of the x and y links of plane z+1 and of the z link of
         // plane z (garbage where the neighbour lies outside the tile: no face
         // reads those); the word of plane z staged
-        int wnext[2], wown[2];
+        int wnext[2] = {0, 0}, wown[2] = {0, 0};
+        if (wraps) {
 #pragma unroll
-        for (int sec = 0; sec < 2; sec++) {
-            bool fx, fy, fz;
-            const int nx_ = link_wrap_mixed(aln[sec], s_al[sec][lxp], link_angle(h, nax[sec]), fx);
-            const int ny_ = link_wrap_mixed(aln[sec], s_al[sec][lyp], link_angle(h, nay[sec]), fy);
-            const int nz_ = link_wrap_mixed(alc[sec], aln[sec], link_angle(h, caz[sec]), fz);
-            wnext[sec] = wrap_word(nx_, ny_, 0, fx, fy, false);
-            wown[sec] = wxy[sec] | wrap_word(0, 0, nz_, false, false, fz);
-            if (owner) s_w[sec][li] = wown[sec];
+            for (int sec = 0; sec < 2; sec++) {
+                bool fx, fy, fz;
+                const int nx_ = link_wrap_mixed(aln[sec], s_al[sec][lxp], link_angle(h, nax[sec]), fx);
+                const int ny_ = link_wrap_mixed(aln[sec], s_al[sec][lyp], link_angle(h, nay[sec]), fy);
+                const int nz_ = link_wrap_mixed(alc[sec], aln[sec], link_angle(h, caz[sec]), fz);
+                wnext[sec] = wrap_word(nx_, ny_, 0, fx, fy, false);
+                wown[sec] = wxy[sec] | wrap_word(0, 0, nz_, false, false, fz);
+                s_w[sec][li] = wown[sec];
+            }
         }
         __syncthreads();
         if (upd) {
@@ -351,8 +358,7 @@ __global__ __launch_bounds__(64 * (WG_TY + 3)) void wind_gauss_tile_kernel(Geom 
                 const int Wz = -(((wrap_n<0>(o) + wrap_n<1>(xp)) - wrap_n<0>(yp)) - wrap_n<1>(o));
                 const int Wx = -(((wrap_n<1>(o) + wrap_n<2>(yp)) - wrap_n<1>(zp)) - wrap_n<2>(o));
                 const int Wy = -(((wrap_n<2>(o) + wrap_n<0>(zp)) - wrap_n<2>(xp)) - wrap_n<0>(o));
-                const int flagged = (wrap_f<0>(o) | wrap_f<1>(o) | wrap_f<2>(o)) | wrap_f<1>(xp) | wrap_f<2>(xp) |
-                                    wrap_f<0>(yp) | wrap_f<2>(yp) | wrap_f<0>(zp) | wrap_f<1>(zp);
+                const int flagged = (o & WRAP_F_XYZ) | (xp & WRAP_F_YZ) | (yp & WRAP_F_XZ) | (zp & WRAP_F_XY);
                 uint8_t byte = WABS_FIX;
                 if (!flagged) {
                     byte = pack_wabs(Wx, Wy, Wz);

@@ -148,9 +148,12 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
     const int lxm = row * LW + max(col - 1, 0), lym = max(row - 1, 0) * LW + col;
 
     // fused diagnostics: the halo sites whose new E_x (column x0 - 1) or E_y
-    // (row y0 - 1) the divergence of an interior site needs
+    // (row y0 - 1) the divergence of an interior site needs; the faces read
+    // phases and wrap counts at the site and at +x and +y only, so the row
+    // y0 - 1 and the column x0 - 1 form neither
     const bool edge_x = FUSE && owner && col == 0 && row >= 1 && row <= TY && gy < g.ny;
     const bool edge_y = FUSE && w == TY && gx < g.nx;
+    const bool wraps = FUSE && owner && row > 0 && col > 0;
 
     const int zbeg = Z0, zend = min(Z0 + TZ, g.nz);
 
@@ -165,8 +168,9 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
     const int it = w * 64 + lx;            // interior thread's slot in FL
     // FP64 diagnostic steps keep their six running sums in LDS, one slot per
     // interior thread (same operations, same order): in registers they would
-    // push the z-march past 256 VGPRs
-    constexpr bool ACC_LDS = DIAG && !FUSE && sizeof(T) == 8;
+    // push the z-march past 256 VGPRs.  So does the fused FP32 step with the
+    // deeper load pipeline, whose registers go to the loads in flight.
+    constexpr bool ACC_LDS = DIAG && (sizeof(T) == 8 || (FUSE && PF >= 1));
     __shared__ double accs[ACC_LDS ? 6 : 1][ACC_LDS ? 64 * TY : 1];
     if constexpr (ACC_LDS) {
         if (interior) {
@@ -279,7 +283,7 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
         // phase of plane z is the one this thread staged one plane before)
         T aln[2] = {T(0), T(0)};
         if constexpr (FUSE) {
-            if (owner && z > zbeg - 1) {
+            if (wraps && z > zbeg - 1) {
 #pragma unroll
                 for (int sec = 0; sec < 2; sec++) alc[sec] = L.v[sec][Q_AN][li];
             }
@@ -295,8 +299,10 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                     L.v[sec][Q_UXI + 2 * i][li] = cU[sec][i].im;
                 }
                 if constexpr (FUSE) {
-                    aln[sec] = phase_of(nf[sec]);
-                    L.v[sec][Q_AN][li] = aln[sec];
+                    if (wraps) {
+                        aln[sec] = phase_of(nf[sec]);
+                        L.v[sec][Q_AN][li] = aln[sec];
+                    }
                 }
             }
         }
@@ -324,17 +330,19 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
         // fused: wrap counts of the x and y links of plane z+1 and of the z
         // link of plane z (garbage where the neighbour lies outside the tile:
         // no face reads those); stage the word of plane z
-        int wnext[2], wown[2];
+        int wnext[2] = {0, 0}, wown[2] = {0, 0};
         if constexpr (FUSE) {
+            if (wraps) {
 #pragma unroll
-            for (int sec = 0; sec < 2; sec++) {
-                bool fx, fy, fz;
-                const int nx_ = link_wrap(aln[sec], L.v[sec][Q_AN][lxp], link_angle(c.h, nA[sec][0]), fx);
-                const int ny_ = link_wrap(aln[sec], L.v[sec][Q_AN][lyp], link_angle(c.h, nA[sec][1]), fy);
-                const int nz_ = link_wrap(alc[sec], aln[sec], link_angle(c.h, cA[sec][2]), fz);
-                wnext[sec] = wrap_word(nx_, ny_, 0, fx, fy, false);
-                wown[sec] = wxy[sec] | wrap_word(0, 0, nz_, false, false, fz);
-                if (owner) FL.nw[sec][li] = wown[sec];
+                for (int sec = 0; sec < 2; sec++) {
+                    bool fx, fy, fz;
+                    const int nx_ = link_wrap(aln[sec], L.v[sec][Q_AN][lxp], link_angle(c.h, nA[sec][0]), fx);
+                    const int ny_ = link_wrap(aln[sec], L.v[sec][Q_AN][lyp], link_angle(c.h, nA[sec][1]), fy);
+                    const int nz_ = link_wrap(alc[sec], aln[sec], link_angle(c.h, cA[sec][2]), fz);
+                    wnext[sec] = wrap_word(nx_, ny_, 0, fx, fy, false);
+                    wown[sec] = wxy[sec] | wrap_word(0, 0, nz_, false, false, fz);
+                    FL.nw[sec][li] = wown[sec];
+                }
             }
         }
         __syncthreads();
@@ -348,8 +356,7 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
                     const int Wz = -(((wrap_n<0>(o) + wrap_n<1>(xp)) - wrap_n<0>(yp)) - wrap_n<1>(o));
                     const int Wx = -(((wrap_n<1>(o) + wrap_n<2>(yp)) - wrap_n<1>(zp)) - wrap_n<2>(o));
                     const int Wy = -(((wrap_n<2>(o) + wrap_n<0>(zp)) - wrap_n<2>(xp)) - wrap_n<0>(o));
-                    const int flagged = (wrap_f<0>(o) | wrap_f<1>(o) | wrap_f<2>(o)) | wrap_f<1>(xp) |
-                                        wrap_f<2>(xp) | wrap_f<0>(yp) | wrap_f<2>(yp) | wrap_f<0>(zp) | wrap_f<1>(zp);
+                    const int flagged = (o & WRAP_F_XYZ) | (xp & WRAP_F_YZ) | (yp & WRAP_F_XZ) | (zp & WRAP_F_XY);
                     uint8_t byte = WABS_FIX;
                     if (!flagged) {
                         const int aWx = abs(Wx), aWy = abs(Wy), aWz = abs(Wz);
@@ -670,9 +677,10 @@ static hipError_t launch_ty(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> 
             if (wabs) {
                 if constexpr (sizeof(T) == 4 && TY != 12) {
                     if (mom.pi[0] == mom_out.pi[0]) return hipErrorInvalidValue;
-                    // (no deeper load pipeline: its registers would spill at 8 rows)
-                    if (nt) MTS_TILE_LAUNCH(true, true, 0, true);
-                    else MTS_TILE_LAUNCH(true, false, 0, true);
+                    // deeper load pipeline, running sums in LDS (512^3: 6.71
+                    // against 6.81 ms per diagnostic step)
+                    if (nt) MTS_TILE_LAUNCH(true, true, 1, true);
+                    else MTS_TILE_LAUNCH(true, false, 1, true);
                 } else {
                     return hipErrorNotSupported;
                 }

@@ -97,14 +97,25 @@ __host__ __device__ inline uint32_t fix_blocks_of(uint32_t S) {
     return chunks < FIX_MAX_BLOCKS ? chunks : FIX_MAX_BLOCKS;
 }
 
+// One of two values, both passed by value: the sector of a listed site is a
+// per-lane value, and indexing the pointer table with it would take an
+// address inside the table (a per-lane pointer load from the argument
+// block, or, for a table built in the kernel, a per-thread copy in scratch).
+template <typename V>
+__device__ __forceinline__ V pick(bool second, V a, V b) {
+    return second ? b : a;
+}
+
 // One marked site of one sector: its three faces evaluated as the post-step
 // kernel does (FP64 from the complex products where the guard asks for it),
 // its byte rewritten; returns |Wx| + |Wy| + |Wz|.
 template <typename T>
 __device__ __forceinline__ int fix_site(const Geom &g, const Fields<T> &f, T h, uint8_t *wabs, uint32_t plane, int sec,
                                         uint32_t s) {
-    const cx<T> *P = f.phi[sec];
-    const T *Ax = f.A[sec][0], *Ay = f.A[sec][1], *Az = f.A[sec][2];
+    const bool q = sec != 0;
+    const cx<T> *P = pick<const cx<T> *>(q, f.phi[0], f.phi[1]);
+    const T *Ax = pick<const T *>(q, f.A[0][0], f.A[1][0]), *Ay = pick<const T *>(q, f.A[0][1], f.A[1][1]),
+            *Az = pick<const T *>(q, f.A[0][2], f.A[1][2]);
     const int x = s % g.nx, y = (s / g.nx) % g.ny, z = s / g.nxy;
     const uint32_t nx = g.nx, nxy = g.nxy;
     const int xp = wrap1(x + 1, g.nx), yp = wrap1(y + 1, g.ny), zp = wrap1(z + 1, g.nz);

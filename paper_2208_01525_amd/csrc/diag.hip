@@ -588,8 +588,12 @@ __global__ __launch_bounds__(1024) void reduce_batch_kernel(const BatchPost<T> *
 }
 
 uint32_t cells_blocks(const Geom &g) {
-    const uint32_t gx = cells_by_words(g) ? (uint32_t)g.nx / 256 : (uint32_t)((g.nx + 63) / 64);
-    return gx * (uint32_t)((g.ny + 3) / 4) * (uint32_t)((g.nz + CZ - 1) / CZ);
+    if (cells_by_words(g)) {
+        const uint32_t rpw = (uint32_t)cells_rows_per_wave(g);
+        const uint32_t gx = rpw == 2 ? 1u : (uint32_t)g.nx / 256;
+        return gx * (((uint32_t)g.ny + 4 * rpw - 1) / (4 * rpw)) * (uint32_t)((g.nz + CZ - 1) / CZ);
+    }
+    return (uint32_t)((g.nx + 63) / 64) * (uint32_t)((g.ny + 3) / 4) * (uint32_t)((g.nz + CZ - 1) / CZ);
 }
 
 template <typename T>

@@ -298,14 +298,17 @@ __device__ __forceinline__ void cells_block(const Geom &g, const uint8_t *wabs, 
 }
 
 
-// Rows whose width is a multiple of 256 take four cells per lane: a block of
-// 64 x 4 lanes covers 256 x 4 columns and walks CZ planes, reading the
-// packed |W| bytes as 32-bit words and adding the six face fields of four
-// cells at once (each field is at most 3, so no byte of the sum carries into
-// the next).  The x neighbour of a lane's last cell is the next lane's first
-// byte (a shuffle; the row's last lane reads it).  With bits, lane k < 4
-// assembles the 64-cell word k of the wave's 256 cells from four ballots.
-__host__ __device__ inline bool cells_by_words(const Geom &g) { return g.nx % 256 == 0; }
+// Rows whose width is a multiple of 256, or exactly 128, take four cells per
+// lane: a wave covers 256 cells of one row (or two rows of 128, one per
+// half-wave), a block of 64 x 4 lanes four such waves, and it walks CZ
+// planes, reading the packed |W| bytes as 32-bit words and adding the six
+// face fields of four cells at once (each field is at most 3, so no byte of
+// the sum carries into the next).  The x neighbour of a lane's last cell is
+// the next lane's first byte (a shuffle; a row's last lane reads it).  With
+// bits, lane k < 4 assembles the 64-cell word k of the wave's 256 cells from
+// four ballots.
+__host__ __device__ inline bool cells_by_words(const Geom &g) { return g.nx % 256 == 0 || g.nx == 128; }
+__host__ __device__ inline int cells_rows_per_wave(const Geom &g) { return g.nx == 128 ? 2 : 1; }
 
 __device__ __forceinline__ uint64_t spread4(uint32_t v) {   // bit i of v (16 bits) to bit 4 i
     uint64_t x = v & 0xFFFFu;
@@ -318,15 +321,19 @@ __device__ __forceinline__ uint64_t spread4(uint32_t v) {   // bit i of v (16 bi
 
 __device__ __forceinline__ void cells4_block(const Geom &g, const uint8_t *wabs, uint8_t *cells, uint64_t *bits,
                                              uint32_t plane, uint32_t nwords, uint32_t blk, int lane, int ty) {
-    const uint32_t gx = (uint32_t)g.nx / 256, gy = (g.ny + 3) / 4;
+    const int rpw = cells_rows_per_wave(g), lpr = 64 / rpw;          // rows per wave, lanes per row
+    const uint32_t gx = rpw == 2 ? 1u : (uint32_t)g.nx / 256, gy = (g.ny + 4 * rpw - 1) / (4 * rpw);
     const uint32_t bx = blk % gx, by = (blk / gx) % gy, bz = blk / (gx * gy);
-    const int x = (int)bx * 256 + 4 * lane;
-    const int y = by * 4 + ty;
-    const bool in = y < g.ny;     // uniform per wave
-    if (!in) return;              // no barrier below: the wave may leave
+    const int lx = lane % lpr;
+    const int x = (int)bx * 256 + 4 * lx;
+    const int y0 = ((int)by * 4 + ty) * rpw;   // the wave's first row
+    if (y0 >= g.ny) return;                    // uniform per wave; no barrier below: the wave may leave
+    const int yl = y0 + lane / lpr;
+    const bool in = yl < g.ny;                 // a second row past the box: loads stay in the first, no stores
+    const int y = in ? yl : y0;
     const int z0 = bz * CZ, z1 = min(z0 + CZ, g.nz);
     const uint32_t col = (uint32_t)x + (uint32_t)g.nx * (uint32_t)y;
-    const uint32_t colx4 = (uint32_t)wrap1(x + 4, g.nx) + (uint32_t)g.nx * (uint32_t)y;   // last lane only
+    const uint32_t colx4 = (uint32_t)wrap1(x + 4, g.nx) + (uint32_t)g.nx * (uint32_t)y;   // a row's last lane only
     const uint32_t coly = (uint32_t)x + (uint32_t)g.nx * (uint32_t)wrap1(y + 1, g.ny);
     constexpr uint32_t M = 0x03030303u;
     uint32_t w0[2];
@@ -343,10 +350,10 @@ __device__ __forceinline__ void cells4_block(const Geom &g, const uint8_t *wabs,
             const uint32_t wz = *reinterpret_cast<const uint32_t *>(w + col + offz);
             const uint32_t wy = *reinterpret_cast<const uint32_t *>(w + coly + off);
             uint32_t nb = (uint32_t)__shfl_down((int)o, 1, 64) & 0xFFu;   // next lane's first cell
-            if (lane == 63) nb = w[colx4 + off];
+            if (lx == lpr - 1) nb = w[colx4 + off];
             const uint32_t wx = (o >> 8) | (nb << 24);
             n[sec] = (o & M) + (wx & M) + ((o >> 2) & M) + ((wy >> 2) & M) + ((o >> 4) & M) + ((wz >> 4) & M);
-            *reinterpret_cast<uint32_t *>(cells + (size_t)sec * plane + col + off) = n[sec];
+            if (in) *reinterpret_cast<uint32_t *>(cells + (size_t)sec * plane + col + off) = n[sec];
             w0[sec] = wz;
         }
         if (bits) {
@@ -359,9 +366,10 @@ __device__ __forceinline__ void cells4_block(const Geom &g, const uint8_t *wabs,
                     const uint64_t b = __ballot(((v >> (8 * j)) & 0xFFu) != 0);
                     word |= spread4((uint32_t)(b >> (16 * (lane & 3)))) << j;
                 }
-                if (lane < 4) {
-                    const uint32_t xw = bx * 4 + (uint32_t)lane;   // word index within the row
-                    const uint32_t wi = xw + (uint32_t)(g.nx / 64) * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
+                const int wrow = y0 + lane * rpw / 4;   // word k < 4: row of the wave's k-th 64 cells
+                if (lane < 4 && wrow < g.ny) {
+                    const uint32_t xw = bx * 4 + (uint32_t)(lane % (4 / rpw));   // word index within the row
+                    const uint32_t wi = xw + (uint32_t)(g.nx / 64) * ((uint32_t)wrow + (uint32_t)g.ny * (uint32_t)z);
                     bits[(size_t)sec * nwords + wi] = word;
                 }
             }

@@ -217,13 +217,14 @@ def test_batch_fused_matches_box_by_box():
 
 
 @pytest.mark.parametrize("precision,rows", [("fp32", 8), ("fp32", 0), ("fp64", 0)])
-@pytest.mark.parametrize("geom", [(256, 6, 5), (512, 5, 18)])
+@pytest.mark.parametrize("geom", [(256, 6, 5), (512, 5, 18), (128, 7, 5), (128, 4, 18)])
 def test_cells_of_wide_rows_match_oracle(geom, precision, rows):
-    """Rows whose width is a multiple of 256 take the cells kernel that reads the packed |W|
-    bytes as words, four cells per lane, and assembles the occupancy words from ballots:
-    cells equal the oracle's cells of the same windings (clipped to 3 per face, what a packed
-    byte holds) and the overlap count the oracle's, on random fields with many windings
-    (ragged y and z blocks; the second box crosses two 16-plane blocks)."""
+    """Rows whose width is a multiple of 256, or 128 (two rows per wave), take the cells
+    kernel that reads the packed |W| bytes as words, four cells per lane, and assembles the
+    occupancy words from ballots: cells equal the oracle's cells of the same windings (clipped
+    to 3 per face, what a packed byte holds) and the overlap count the oracle's, on random
+    fields with many windings (ragged y and z blocks, an odd row count that leaves a wave's
+    second row outside the box; the 18-plane boxes cross two 16-plane blocks)."""
     nx, ny, nz = geom
     st = I.random_full(nx, ny, nz, 61, link=0.7, mom=0.4)
     if precision == "fp32":

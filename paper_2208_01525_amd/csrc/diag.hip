@@ -216,9 +216,11 @@ __global__ __launch_bounds__(64 * (WG_TY + 3)) void wind_gauss_tile_kernel(Geom 
                                                                             Partials part) {
     static_assert(sizeof(T) == 8, "FP64 fields");
     constexpr int TY = WG_TY, R = TY + 2, LW = WG_LW;
-    __shared__ float s_al[2][R * LW];              // alpha of plane z+1
-    __shared__ T s_ex[2][R * LW], s_ey[2][R * LW]; // E_x, E_y (n + 1/2) of plane z
-    __shared__ int s_w[2][R * LW];                 // packed wrap counts of plane z
+    // two buffers by plane parity, so that a plane's stores never meet the
+    // previous plane's loads and the plane ends without a barrier
+    __shared__ float s_al[2][2][R * LW];                 // alpha of plane z+1
+    __shared__ T s_ex[2][2][R * LW], s_ey[2][2][R * LW]; // E_x, E_y (n + 1/2) of plane z
+    __shared__ int s_w[2][2][R * LW];                    // packed wrap counts of plane z
     const int ntx = (g.nx + 63) / 64, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + WG_TZ - 1) / WG_TZ;
     const uint32_t t = xcd_order(blockIdx.x, (uint32_t)(ntx * nty * ntz));
     const int X0 = (int)(t % ntx) * 64, Y0 = (int)((t / ntx) % nty) * TY, Z0 = (int)(t / (ntx * nty)) * WG_TZ;
@@ -274,14 +276,19 @@ __global__ __launch_bounds__(64 * (WG_TY + 3)) void wind_gauss_tile_kernel(Geom 
         const uint32_t sn = colidx + g.nxy * (uint32_t)zbeg;
 #pragma unroll
         for (int sec = 0; sec < 2; sec++) {
-            cf[sec] = f.phi[sec][s];
-            alc[sec] = phase_f32(cf[sec]);
-            caz[sec] = f.A[sec][2][s];
+            cf[sec] = pf[sec] = cx<T>{T(0), T(0)};
+            alc[sec] = 0.f;
+            caz[sec] = pax[sec] = pay[sec] = paz[sec] = T(0);
+            if (wraps) {   // phi and A only where wrap counts are formed (interior sites among them)
+                cf[sec] = f.phi[sec][s];
+                alc[sec] = phase_f32(cf[sec]);
+                caz[sec] = f.A[sec][2][s];
+                pf[sec] = f.phi[sec][sn];
+                pax[sec] = f.A[sec][0][sn];
+                pay[sec] = f.A[sec][1][sn];
+                paz[sec] = f.A[sec][2][sn];
+            }
             if (interior) ezp[sec] = mom.E[sec][2][s];
-            pf[sec] = f.phi[sec][sn];
-            pax[sec] = f.A[sec][0][sn];
-            pay[sec] = f.A[sec][1][sn];
-            paz[sec] = f.A[sec][2][sn];
             pex[sec] = pey[sec] = pez[sec] = T(0);
             ppi[sec] = cx<T>{T(0), T(0)};
         }
@@ -289,6 +296,7 @@ __global__ __launch_bounds__(64 * (WG_TY + 3)) void wind_gauss_tile_kernel(Geom 
     double acc[6] = {0, 0, 0, 0, 0, 0};   // gauss |C| p, q; scale p, q; wind p, q
     for (int z = zbeg - 1; z < zend; z++) {
         const bool upd = interior && z >= zbeg;
+        const int pb = (z - zbeg + 1) & 1;   // this plane's LDS buffers
         const uint32_t s = colidx + g.nxy * (uint32_t)wrapn(z, g.nz);
         cx<T> nf[2], pic[2];
         T nax[2], nay[2], naz[2], exc[2], eyc[2], ezc[2];
@@ -308,10 +316,12 @@ __global__ __launch_bounds__(64 * (WG_TY + 3)) void wind_gauss_tile_kernel(Geom 
             const uint32_t s2 = colidx + g.nxy * (uint32_t)wrapn(z + 2, g.nz);
 #pragma unroll
             for (int sec = 0; sec < 2; sec++) {
-                pf[sec] = f.phi[sec][s2];
-                pax[sec] = f.A[sec][0][s2];
-                pay[sec] = f.A[sec][1][s2];
-                paz[sec] = f.A[sec][2][s2];
+                if (wraps) {
+                    pf[sec] = f.phi[sec][s2];
+                    pax[sec] = f.A[sec][0][s2];
+                    pay[sec] = f.A[sec][1][s2];
+                    paz[sec] = f.A[sec][2][s2];
+                }
                 if (need_ex) pex[sec] = mom.E[sec][0][s1];
                 if (need_ey) pey[sec] = mom.E[sec][1][s1];
                 if (interior) {
@@ -325,11 +335,11 @@ __global__ __launch_bounds__(64 * (WG_TY + 3)) void wind_gauss_tile_kernel(Geom 
         for (int sec = 0; sec < 2; sec++) {
             if (wraps) {
                 aln[sec] = phase_f32(nf[sec]);
-                s_al[sec][li] = aln[sec];
+                s_al[pb][sec][li] = aln[sec];
             }
             if (z >= zbeg) {
-                if (need_ex) s_ex[sec][li] = exc[sec];
-                if (need_ey) s_ey[sec][li] = eyc[sec];
+                if (need_ex) s_ex[pb][sec][li] = exc[sec];
+                if (need_ey) s_ey[pb][sec][li] = eyc[sec];
             }
         }
         __syncthreads();
@@ -341,12 +351,12 @@ __global__ __launch_bounds__(64 * (WG_TY + 3)) void wind_gauss_tile_kernel(Geom 
 #pragma unroll
             for (int sec = 0; sec < 2; sec++) {
                 bool fx, fy, fz;
-                const int nx_ = link_wrap_mixed(aln[sec], s_al[sec][lxp], link_angle(h, nax[sec]), fx);
-                const int ny_ = link_wrap_mixed(aln[sec], s_al[sec][lyp], link_angle(h, nay[sec]), fy);
+                const int nx_ = link_wrap_mixed(aln[sec], s_al[pb][sec][lxp], link_angle(h, nax[sec]), fx);
+                const int ny_ = link_wrap_mixed(aln[sec], s_al[pb][sec][lyp], link_angle(h, nay[sec]), fy);
                 const int nz_ = link_wrap_mixed(alc[sec], aln[sec], link_angle(h, caz[sec]), fz);
                 wnext[sec] = wrap_word(nx_, ny_, 0, fx, fy, false);
                 wown[sec] = wxy[sec] | wrap_word(0, 0, nz_, false, false, fz);
-                s_w[sec][li] = wown[sec];
+                s_w[pb][sec][li] = wown[sec];
             }
         }
         __syncthreads();
@@ -354,7 +364,7 @@ __global__ __launch_bounds__(64 * (WG_TY + 3)) void wind_gauss_tile_kernel(Geom 
 #pragma unroll
             for (int sec = 0; sec < 2; sec++) {
                 // windings through the three faces at the site (lower corner x)
-                const int o = wown[sec], xp = s_w[sec][lxp], yp = s_w[sec][lyp], zp = wnext[sec];
+                const int o = wown[sec], xp = s_w[pb][sec][lxp], yp = s_w[pb][sec][lyp], zp = wnext[sec];
                 const int Wz = -(((wrap_n<0>(o) + wrap_n<1>(xp)) - wrap_n<0>(yp)) - wrap_n<1>(o));
                 const int Wx = -(((wrap_n<1>(o) + wrap_n<2>(yp)) - wrap_n<1>(zp)) - wrap_n<2>(o));
                 const int Wy = -(((wrap_n<2>(o) + wrap_n<0>(zp)) - wrap_n<2>(xp)) - wrap_n<0>(o));
@@ -366,13 +376,12 @@ __global__ __launch_bounds__(64 * (WG_TY + 3)) void wind_gauss_tile_kernel(Geom 
                 }
                 wabs[(size_t)sec * plane + s] = byte;
                 // Gauss residual at n + 1/2: div E^{n+1/2} - g Im[conj(phi^n) Pi^{n+1/2}]
-                const T div = gauss_div(s_ex[sec][li], s_ex[sec][lxm], s_ey[sec][li], s_ey[sec][lym], ezc[sec],
+                const T div = gauss_div(s_ex[pb][sec][li], s_ex[pb][sec][lxm], s_ey[pb][sec][li], s_ey[pb][sec][lym], ezc[sec],
                                         ezp[sec], inv_h);
                 gauss_accumulate(div, gauss_charge(gs[sec], cf[sec], pic[sec]), acc[sec], acc[2 + sec]);
                 ezp[sec] = ezc[sec];
             }
         }
-        __syncthreads();   // LDS of plane z is reused by plane z+1
 #pragma unroll
         for (int sec = 0; sec < 2; sec++) {
             cf[sec] = nf[sec];

@@ -116,7 +116,8 @@ size_t mts_state_bytes(const mts_params *p);
  *   out         receives the context.
  * The library allocates its own device scratch (reduction partials; the
  * phase of each scalar, 2 elements per site; winding and cell bytes, 4
- * bytes per site; occupancy bits; a diagnostic ring); ENOMEM if that
+ * bytes per site; occupancy bits; the list of sites whose windings the
+ * FP64 fix-up evaluates, 4 MiB; a diagnostic ring); ENOMEM if that
  * fails. */
 int mts_create(const mts_params *p, void *dev_state, size_t state_bytes, void *stream, mts_ctx **out);
 
@@ -286,7 +287,10 @@ int mts_get_prefetch(const mts_ctx *ctx, int32_t *on);
  * the post-step kernels and mts_get_fused_diagnostics reports 0.  Windings,
  * cells and overlap counts are bitwise identical either way; the Gauss sums
  * agree to the rounding of their summation order.  FP64 and the per-site
- * kernel always use the post-step kernels.  Synchronises the stream. */
+ * kernel always use post-step kernels (FP64: one tiled pass for windings
+ * and the Gauss residual, with FP32 phases and FP64 wrap decisions and the
+ * same FP64 fix-up, so the windings are those of an FP64 evaluation bit for
+ * bit).  Synchronises the stream. */
 int mts_set_fused_diagnostics(mts_ctx *ctx, int32_t rows);
 int mts_get_fused_diagnostics(const mts_ctx *ctx, int32_t *rows);
 

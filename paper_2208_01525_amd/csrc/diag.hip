@@ -376,8 +376,8 @@ __global__ __launch_bounds__(64 * (WG_TY + 3)) void wind_gauss_tile_kernel(Geom 
                 }
                 wabs[(size_t)sec * plane + s] = byte;
                 // Gauss residual at n + 1/2: div E^{n+1/2} - g Im[conj(phi^n) Pi^{n+1/2}]
-                const T div = gauss_div(s_ex[pb][sec][li], s_ex[pb][sec][lxm], s_ey[pb][sec][li], s_ey[pb][sec][lym], ezc[sec],
-                                        ezp[sec], inv_h);
+                const T div = gauss_div(s_ex[pb][sec][li], s_ex[pb][sec][lxm], s_ey[pb][sec][li],
+                                        s_ey[pb][sec][lym], ezc[sec], ezp[sec], inv_h);
                 gauss_accumulate(div, gauss_charge(gs[sec], cf[sec], pic[sec]), acc[sec], acc[2 + sec]);
                 ezp[sec] = ezc[sec];
             }

@@ -315,6 +315,11 @@ bool diag_fused(const mts_ctx *c) {
 
 TileShape fused_tile(const mts_ctx *c) { return TileShape{c->fuse_ty, c->tile.tz}; }
 
+// Diagnostic steps that are not fused take the tiled winding/Gauss pass and
+// the fix-up, unless the box has 2^31 sites or more (the fix-up list holds a
+// site in 31 bits): those take the per-column kernel.
+bool post_tiled(const mts_ctx *c) { return c->S < (1ull << 31); }
+
 // Partials per slot: the update kernel's blocks for the integer-time sums,
 // the per-site grid for the post-step diagnostic kernels.
 // The second table (at nblk_dev + NSLOT) is the fused path's: the update
@@ -323,11 +328,11 @@ hipError_t upload_nblk(mts_ctx *c) {
     uint32_t nb[2 * NSLOT];
     const uint32_t step_blocks = diag_per_site(c) ? site_blocks(c->g) : tile_blocks(c->g, diag_tile(c));
     const uint32_t fused_blocks = c->fuse_ty ? tile_blocks(c->g, fused_tile(c)) : 0;
-    // FP64: the tiled winding/Gauss kernel and the fix-up passes; FP32
-    // without fusion: the per-column winding/Gauss kernel
-    const bool fp64 = c->p.precision == MTS_FP64;
-    const uint32_t wblk = fp64 ? wind_tile_blocks(c->g) : wind_blocks(c->g);
-    const uint32_t fixblk = fp64 ? wind_fix_blocks(c->g) : 0;
+    // diagnostic steps that are not fused: the tiled winding/Gauss pass and
+    // the fix-up passes (the per-column kernel in boxes of 2^31 sites or more)
+    const bool tiled = post_tiled(c);
+    const uint32_t wblk = tiled ? wind_tile_blocks(c->g) : wind_blocks(c->g);
+    const uint32_t fixblk = tiled ? wind_fix_blocks(c->g) : 0;
     for (int q = 0; q < NSLOT; q++) {
         nb[q] = q <= SL_GV ? step_blocks : (q <= SL_WIND_Q ? wblk : (q <= SL_OV_Q ? overlap_blocks(c->g) : fixblk));
         nb[NSLOT + q] = q <= SL_WIND_Q ? fused_blocks : (q <= SL_OV_Q ? overlap_blocks(c->g) : wind_fix_blocks(c->g));
@@ -350,18 +355,17 @@ hipError_t enqueue_diag_post(mts_ctx *c, const Book &b, double eta_j, double s, 
     for (int q = 0; q < 2; q++) gcoef[q] = 2.0 * e2[q] * b.An * (1.0 + b.delta) / (1.0 + b.omega);
     T *alpha = static_cast<T *>(c->alpha);
     hipError_t e = hipSuccess;
-    if (!fused && sizeof(T) == 8) {
-        // FP64: windings (wrap counts) and the Gauss residual in one tiled
-        // pass, then the fix-up of the flagged sites
-        if constexpr (sizeof(T) == 8) {
-            e = launch_wind_gauss_tile<T>(c->g, fields_of<T>(c, c->cur), moms_of<T>(c), (T)p.dx, (T)(1.0 / p.dx),
-                                          gcoef, c->wabs, (uint32_t)c->plane, part, st);
-            if (e == hipSuccess)
-                e = launch_wind_fix<T>(c->g, fields_of<T>(c, c->cur), (T)p.dx, c->wabs, (uint32_t)c->plane, part,
-                                       c->fixlist, st);
-        }
-        (void)alpha;
+    if (!fused && post_tiled(c)) {
+        // windings (wrap counts) and the Gauss residual in one tiled pass,
+        // then the fix-up of the flagged sites
+        e = launch_wind_gauss_tile<T>(c->g, fields_of<T>(c, c->cur), moms_of<T>(c), (T)p.dx, (T)(1.0 / p.dx), gcoef,
+                                      c->wabs, (uint32_t)c->plane, part, st);
+        if (e == hipSuccess)
+            e = launch_wind_fix<T>(c->g, fields_of<T>(c, c->cur), (T)p.dx, c->wabs, (uint32_t)c->plane, part,
+                                   c->fixlist, st);
     } else if (!fused) {
+        // boxes of 2^31 sites or more (the fix-up list holds a site in 31
+        // bits): the per-column kernel, which evaluates flagged links in place
         if (!alpha_ready) e = launch_phase<T>(c->g, fields_of<T>(c, c->cur), alpha, (uint32_t)c->plane, st);
         if (e == hipSuccess)
             e = launch_wind_gauss<T>(c->g, fields_of<T>(c, c->cur), moms_of<T>(c), alpha, (T)p.dx, (T)(1.0 / p.dx),

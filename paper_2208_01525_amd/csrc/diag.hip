@@ -145,12 +145,13 @@ hipError_t launch_wind_gauss(const Geom &g, Fields<T> f, Moms<T> mom, const T *a
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- windings and Gauss, tiled (FP64)
+// ---------------------------------------------------------------- windings and Gauss, tiled
 //
-// The FP64 diagnostic step's windings and Gauss residual in one z-marching
-// pass over 64 x WG_TY tiles with a one-site halo, as the fused FP32
-// diagnostic tile forms them (the FP64 update tile has no registers left to
-// do it in place): each site's phase alpha of plane z+1 and the new E_x, E_y
+// The windings and Gauss residual of a diagnostic step that is not fused
+// (FP64, whose update tile has no registers left to do it in place; FP32
+// with fusion off, on the per-site kernel, or where no second momentum copy
+// fits) in one z-marching pass over 64 x WG_TY tiles with a one-site halo,
+// as the fused FP32 diagnostic tile forms them: each site's phase alpha of plane z+1 and the new E_x, E_y
 // of plane z go through LDS; each link's wrap count is formed once and
 // packed with its site's others; the winding through a face is minus the
 // oriented sum of its four links' counts; a flagged link (guard, or a count
@@ -159,8 +160,10 @@ hipError_t launch_wind_gauss(const Geom &g, Fields<T> f, Moms<T> mom, const T *a
 // each plane's loads issued one plane ahead so that they are in flight
 // across the previous plane's barriers.
 //
-// The phases are FP32 (atan2_fast of the FP64 phi, both components first
-// scaled by one power of two, which is exact), the wrap decision FP64:
+// For FP32 fields the phases and wrap counts are the fused tile's (the FP32
+// guard).  For FP64 fields the phases are FP32 (atan2_fast of the FP64 phi,
+// both components first scaled by one power of two, which is exact), the
+// wrap decision FP64:
 // v = (alpha_b - alpha_a) - h A in double from the widened phases.  Each
 // phase is within 5e-7 rad of the FP64 one (4e-7 from atan2_fast, 6e-8
 // from rounding the scaled components), so v is within about 1e-6 of its
@@ -202,6 +205,18 @@ __device__ __forceinline__ int link_wrap_mixed(float aa, float ab, double hA, bo
     return flag ? 0 : (int)n;
 }
 
+// The pass's phase and wrap count per precision: FP64 fields as above; FP32
+// fields exactly as the fused FP32 tile forms them (atan2_fast, the FP32
+// guard, whose |h A| bound keeps every unflagged count inside the field).
+__device__ __forceinline__ float tile_phase(cx<double> p) { return phase_f32(p); }
+__device__ __forceinline__ float tile_phase(cx<float> p) { return phase_of(p); }
+__device__ __forceinline__ int tile_wrap(float aa, float ab, double hA, bool &flag) {
+    return link_wrap_mixed(aa, ab, hA, flag);
+}
+__device__ __forceinline__ int tile_wrap(float aa, float ab, float hA, bool &flag) {
+    return link_wrap(aa, ab, hA, flag);
+}
+
 }  // namespace
 
 uint32_t wind_tile_blocks(const Geom &g) {
@@ -209,12 +224,18 @@ uint32_t wind_tile_blocks(const Geom &g) {
            (uint32_t)((g.nz + WG_TZ - 1) / WG_TZ);
 }
 
+// FP32: two workgroups per CU (at most 80 VGPRs); FP64 keeps its 3 waves per SIMD
 template <typename T>
-__global__ __launch_bounds__(64 * (WG_TY + 3)) void wind_gauss_tile_kernel(Geom g, Fields<T> f, Moms<T> mom, T h,
+constexpr int wind_tile_waves() {
+    return sizeof(T) == 4 ? 6 : 3;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64 * (WG_TY + 3)) __attribute__((amdgpu_waves_per_eu(wind_tile_waves<T>())))
+void wind_gauss_tile_kernel(Geom g, Fields<T> f, Moms<T> mom, T h,
                                                                             T inv_h, double g_p, double g_q,
                                                                             uint8_t *wabs, uint32_t plane,
                                                                             Partials part) {
-    static_assert(sizeof(T) == 8, "FP64 fields");
     constexpr int TY = WG_TY, R = TY + 2, LW = WG_LW;
     // two buffers by plane parity, so that a plane's stores never meet the
     // previous plane's loads and the plane ends without a barrier
@@ -281,7 +302,7 @@ __global__ __launch_bounds__(64 * (WG_TY + 3)) void wind_gauss_tile_kernel(Geom 
             caz[sec] = pax[sec] = pay[sec] = paz[sec] = T(0);
             if (wraps) {   // phi and A only where wrap counts are formed (interior sites among them)
                 cf[sec] = f.phi[sec][s];
-                alc[sec] = phase_f32(cf[sec]);
+                alc[sec] = tile_phase(cf[sec]);
                 caz[sec] = f.A[sec][2][s];
                 pf[sec] = f.phi[sec][sn];
                 pax[sec] = f.A[sec][0][sn];
@@ -334,7 +355,7 @@ __global__ __launch_bounds__(64 * (WG_TY + 3)) void wind_gauss_tile_kernel(Geom 
 #pragma unroll
         for (int sec = 0; sec < 2; sec++) {
             if (wraps) {
-                aln[sec] = phase_f32(nf[sec]);
+                aln[sec] = tile_phase(nf[sec]);
                 s_al[pb][sec][li] = aln[sec];
             }
             if (z >= zbeg) {
@@ -351,9 +372,9 @@ __global__ __launch_bounds__(64 * (WG_TY + 3)) void wind_gauss_tile_kernel(Geom 
 #pragma unroll
             for (int sec = 0; sec < 2; sec++) {
                 bool fx, fy, fz;
-                const int nx_ = link_wrap_mixed(aln[sec], s_al[pb][sec][lxp], link_angle(h, nax[sec]), fx);
-                const int ny_ = link_wrap_mixed(aln[sec], s_al[pb][sec][lyp], link_angle(h, nay[sec]), fy);
-                const int nz_ = link_wrap_mixed(alc[sec], aln[sec], link_angle(h, caz[sec]), fz);
+                const int nx_ = tile_wrap(aln[sec], s_al[pb][sec][lxp], link_angle(h, nax[sec]), fx);
+                const int ny_ = tile_wrap(aln[sec], s_al[pb][sec][lyp], link_angle(h, nay[sec]), fy);
+                const int nz_ = tile_wrap(alc[sec], aln[sec], link_angle(h, caz[sec]), fz);
                 wnext[sec] = wrap_word(nx_, ny_, 0, fx, fy, false);
                 wown[sec] = wxy[sec] | wrap_word(0, 0, nz_, false, false, fz);
                 s_w[pb][sec][li] = wown[sec];
@@ -401,6 +422,8 @@ hipError_t launch_wind_gauss_tile(const Geom &g, Fields<T> f, Moms<T> mom, T h, 
     return hipGetLastError();
 }
 
+template hipError_t launch_wind_gauss_tile<float>(const Geom &, Fields<float>, Moms<float>, float, float,
+                                                  const double[2], uint8_t *, uint32_t, Partials, hipStream_t);
 template hipError_t launch_wind_gauss_tile<double>(const Geom &, Fields<double>, Moms<double>, double, double,
                                                    const double[2], uint8_t *, uint32_t, Partials, hipStream_t);
 

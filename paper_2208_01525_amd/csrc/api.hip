@@ -301,9 +301,18 @@ TileShape diag_tile(const mts_ctx *c) {
 // Diagnostic steps run on the per-site kernel only where the plain steps do.
 bool diag_per_site(const mts_ctx *c) { return c->tile.ty == 0; }
 
-// The tiled FP32 diagnostic step writes the phases alpha of phi^n itself; the
-// per-site kernel and the FP64 tiled one leave them to the phase kernel.
-bool diag_writes_alpha(const mts_ctx *c) { return !diag_per_site(c) && c->p.precision == MTS_FP32; }
+// Diagnostic steps that are not fused take the tiled winding/Gauss pass and
+// the fix-up, unless the box has 2^31 sites or more (the fix-up list holds a
+// site in 31 bits): those take the per-column kernel.
+bool post_tiled(const mts_ctx *c) { return c->S < (1ull << 31); }
+
+// The phases alpha of phi^n for the per-column winding kernel: the tiled
+// unfused FP32 diagnostic step stores them itself; the per-site kernel and
+// the FP64 tiled one leave them to the phase kernel.  Where the tiled pass
+// runs nothing reads them and nothing stores them.
+bool diag_writes_alpha(const mts_ctx *c) {
+    return !diag_per_site(c) && c->p.precision == MTS_FP32 && !post_tiled(c);
+}
 
 // Diagnostic steps of the tiled FP32 kernel take the windings and the Gauss
 // residual in the same pass (the post-step kernels then only form the cells
@@ -315,10 +324,6 @@ bool diag_fused(const mts_ctx *c) {
 
 TileShape fused_tile(const mts_ctx *c) { return TileShape{c->fuse_ty, c->tile.tz}; }
 
-// Diagnostic steps that are not fused take the tiled winding/Gauss pass and
-// the fix-up, unless the box has 2^31 sites or more (the fix-up list holds a
-// site in 31 bits): those take the per-column kernel.
-bool post_tiled(const mts_ctx *c) { return c->S < (1ull << 31); }
 
 // Partials per slot: the update kernel's blocks for the integer-time sums,
 // the per-site grid for the post-step diagnostic kernels.
@@ -431,7 +436,8 @@ int do_step(mts_ctx *c, int32_t n, double eta, double era_m, double s) {
                                ? launch_step<T>(c->g, in, out, mom, coef, diag, part, c->stream)
                                : launch_step_tile<T>(c->g, in, out, mom, mom_out, coef, diag, part,
                                                      fused ? fused_tile(c) : (diag ? diag_tile(c) : c->tile),
-                                                     static_cast<T *>(c->alpha), fused ? c->wabs : nullptr,
+                                                     diag_writes_alpha(c) ? static_cast<T *>(c->alpha) : nullptr,
+                                                     fused ? c->wabs : nullptr,
                                                      (uint32_t)c->plane, c->nt, c->pf, c->xcd, c->stream);
             if (e != hipSuccess) return hipfail(c, e, "step kernel launch");
         }
@@ -1465,7 +1471,7 @@ int batch_upload_boxes(mts_batch *b) {
             x.mom[0] = moms_at<T>(c, 0);
             x.mom[1] = moms_at<T>(c, c->mom2 ? 1 : 0);
             x.part = Partials{c->partials, c->maxblk};
-            x.alpha = static_cast<T *>(c->alpha);
+            x.alpha = diag_writes_alpha(c) ? static_cast<T *>(c->alpha) : nullptr;
             x.wabs = c->wabs;
             x.plane = (uint32_t)c->plane;
             x.tz = b->tz[k];

@@ -472,11 +472,14 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
             }
             if constexpr (DIAG) {
                 if constexpr (!FUSE && sizeof(T) == 4) {
-                    // phase of phi^n for the winding kernel (NaN where phi = 0); in
-                    // FP64 the phase kernel writes them (its atan2 here would spill)
+                    // phase of phi^n for the per-column winding kernel (NaN where
+                    // phi = 0), where that kernel runs (alpha non-null); in FP64
+                    // its atan2 here would spill
+                    if (alpha != nullptr) {
 #pragma unroll
-                    for (int sec = 0; sec < 2; sec++)
-                        st_stream<NT>(alpha + (size_t)sec * plane + s, phase_of(cf[sec]));
+                        for (int sec = 0; sec < 2; sec++)
+                            st_stream<NT>(alpha + (size_t)sec * plane + s, phase_of(cf[sec]));
+                    }
                 }
                 const T dp = mod2[0] - c.sig2[0], dq = mod2[1] - c.sig2[1];
                 const T Vint = c.kap0 * dp * dq;

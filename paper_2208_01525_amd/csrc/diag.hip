@@ -151,14 +151,17 @@ hipError_t launch_wind_gauss(const Geom &g, Fields<T> f, Moms<T> mom, const T *a
 // (FP64, whose update tile has no registers left to do it in place; FP32
 // with fusion off, on the per-site kernel, or where no second momentum copy
 // fits) in one z-marching pass over 64 x WG_TY tiles with a one-site halo,
-// as the fused FP32 diagnostic tile forms them: each site's phase alpha of plane z+1 and the new E_x, E_y
-// of plane z go through LDS; each link's wrap count is formed once and
-// packed with its site's others; the winding through a face is minus the
-// oriented sum of its four links' counts; a flagged link (guard, or a count
-// beyond the packed field) marks the site WABS_FIX for the FP64 fix-up
-// passes.  It reads phi, A, E and Pi once per site (the halo rows from L2),
-// each plane's loads issued one plane ahead so that they are in flight
-// across the previous plane's barriers.
+// as the fused FP32 diagnostic tile forms them: each site's phase alpha of
+// plane z+1 and the new E_x, E_y of plane z go through LDS; each link's wrap
+// count is formed once and packed with its site's others; the winding
+// through a face is minus the oriented sum of its four links' counts; a
+// flagged link (guard, or a count beyond the packed field) marks the site
+// WABS_FIX for the FP64 fix-up passes.  It reads phi, A, E and Pi once per
+// site (the halo rows from L2), each plane's loads issued one plane ahead so
+// that they are in flight across the previous plane's barriers.
+//
+// The Gauss residual is summed in FP64 from the per-site terms of the
+// fields' own precision, as in the fused tile.
 //
 // For FP32 fields the phases and wrap counts are the fused tile's (the FP32
 // guard).  For FP64 fields the phases are FP32 (atan2_fast of the FP64 phi,
@@ -170,8 +173,7 @@ hipError_t launch_wind_gauss(const Geom &g, Fields<T> f, Moms<T> mom, const T *a
 // FP64 value, and a link with |chi| <= pi - MIXED_CUT has the same count as
 // in FP64; every other link, and every link with a zero, NaN or infinite
 // phi at an end, is flagged and its faces evaluated in FP64 by the fix-up.
-// The windings are therefore those of the FP64 evaluation bit for bit; the
-// Gauss residual is FP64 throughout.
+// The windings are therefore those of the FP64 evaluation bit for bit.
 
 namespace {
 

@@ -271,9 +271,11 @@ __device__ __forceinline__ void tile_step(const Geom &g, const Fields<T> &in, co
         if constexpr (FUSE) {
             // the component chosen among loaded pointer values (prvalues: a
             // conditional over the struct's lvalues, or a runtime index, would
-            // select addresses inside it): in the ensemble kernel the pointer
-            // table is a local value, which an address taken into it puts in a
-            // per-thread array (the compiler moved it to LDS, 64 B a thread)
+            // select addresses inside it, per lane): for a single box each lane
+            // then loaded its pointer from the argument block before loading E,
+            // a dependent round trip every plane; in the ensemble kernel, whose
+            // pointer table is a local value, the table became a per-thread
+            // array (the compiler moved it to LDS, 64 B a thread)
             if ((edge_x || edge_y) && z >= zbeg) {
 #pragma unroll
                 for (int sec = 0; sec < 2; sec++) {
@@ -690,8 +692,8 @@ static hipError_t launch_ty(const Geom &g, Fields<T> in, Fields<T> out, Moms<T> 
             if (wabs) {
                 if constexpr (sizeof(T) == 4 && TY != 12) {
                     if (mom.pi[0] == mom_out.pi[0]) return hipErrorInvalidValue;
-                    // deeper load pipeline, running sums in LDS (512^3: 6.71
-                    // against 6.81 ms per diagnostic step)
+                    // deeper load pipeline, running sums in LDS (512^3: 6.17
+                    // against 6.33 ms per diagnostic step)
                     if (nt) MTS_TILE_LAUNCH(true, true, 1, true);
                     else MTS_TILE_LAUNCH(true, false, 1, true);
                 } else {

@@ -1330,7 +1330,7 @@ int mts_autotune_cached(mts_ctx *c, int32_t steps, const char *cache_path, int32
         }
         if (rc != MTS_ENOMEM && rc != MTS_EINVAL) return rc;
         // a choice this context cannot take (no room for a second momentum
-        // copy, a shape this build no longer has): tune afresh
+        // copy, a tile shape the library no longer supports): tune afresh
         c->err.clear();
     }
     double ms = 0.0;
